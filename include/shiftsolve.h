@@ -1,0 +1,222 @@
+/*
+ * shiftsolve -- many shifted linear systems on one MI355X (gfx950).
+ *
+ * The library solves, for thousands of complex shifts sigma_j,
+ *
+ *     (A - sigma_j I) X_j = B,      G_j = C X_j = C (A - sigma_j I)^{-1} B,
+ *
+ * following Bosner, Bujanovic and Drmac, "Parallel solver for shifted
+ * systems in a hybrid CPU-GPU framework" (arXiv 1708.06290):
+ *
+ *   1. once per system, an orthogonal reduction to controller-Hessenberg
+ *      form (Algorithm 1, Section 2): H = Q^T A Q is m-Hessenberg
+ *      (H(i,j) = 0 for i > j + m), R = Q^T B is upper triangular with only
+ *      its first m rows nonzero, Ct = C Q;
+ *   2. per shift, an RQ factorisation H - sigma I = R_sigma Q_sigma computed
+ *      from the last column to the first with an (m+1)-column sliding window
+ *      (Section 3.1), of which only R_sigma(1:m,1:m) is kept: the
+ *      back-substitution Y_j = R_sigma(1:m,1:m)^{-1} R(1:m,:) is fused into
+ *      the last m steps, then X_j = Q_sigma^*(:,1:m) Y_j (Section 3, items 1-3
+ *      of the introduction to that section, and the per-shift right-hand-side
+ *      variant of Section 3.3) and G_j = Ct X_j.
+ *
+ * Sign convention: the paper's transfer function is C (sigma I - A)^{-1} B;
+ * this library returns G_j = C (A - sigma_j I)^{-1} B, i.e. minus that value.
+ *
+ * Data conventions used by every entry point:
+ *   - matrices are column-major; "ld" arguments are leading dimensions in
+ *     elements (ld >= number of rows);
+ *   - complex arrays are interleaved (re, im) double pairs, the layout of C99
+ *     `double _Complex` and of torch.complex128;
+ *   - pointers documented as "device" must point to memory of the GPU that
+ *     is current when the call is made; the library never takes ownership of
+ *     caller memory;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *     calls documented as asynchronous enqueue work on it and return.
+ *
+ * Error convention: 0 on success; a negative value -i means argument i
+ * (1-based) is invalid; positive values are SHS_ERR_* codes.  No exception
+ * crosses this interface.  shs_strerror() turns any code into text.
+ */
+#ifndef SHIFTSOLVE_H
+#define SHIFTSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHS_ABI_VERSION 1
+
+/* return codes (positive) */
+#define SHS_ERR_NOMEM        1  /* device allocation failed or budget exceeded */
+#define SHS_ERR_HIP          2  /* a HIP runtime call failed */
+#define SHS_ERR_UNSUPPORTED  3  /* shape outside what the kernels support */
+#define SHS_ERR_BUSY         4  /* resource in use (serving: queue full) */
+#define SHS_ERR_NOTFOUND     5  /* unknown id (serving) */
+#define SHS_ERR_TIMEOUT      6  /* wait timed out (serving) */
+
+/* per-shift status codes written by shs_solve */
+#define SHS_STATUS_OK             0
+#define SHS_STATUS_SINGULAR       1  /* a diagonal entry of R_sigma is exactly 0 */
+#define SHS_STATUS_NONFINITE      2  /* a NaN or Inf appeared in the result */
+#define SHS_STATUS_FALLBACK       3  /* mixed precision did not converge; FP64 result */
+#define SHS_STATUS_NOT_CONVERGED  4  /* refinement stopped above tol, no fallback */
+
+/* solve modes */
+#define SHS_MODE_FP64         0  /* FP64 sweep */
+#define SHS_MODE_FP32_REFINE  1  /* complex FP32 sweep + FP64 iterative refinement */
+
+/* output selection bits */
+#define SHS_OUT_X    1  /* write X (reduced coordinates) */
+#define SHS_OUT_G    2  /* write G */
+#define SHS_OUT_ETA  4  /* compute the FP64 backward error of every shift */
+
+/* largest supported m (number of inputs, columns of B) */
+#define SHS_MAX_M 16
+
+typedef struct shs_handle shs_handle;
+
+typedef struct shs_config {
+    int32_t abi_version;   /* must be SHS_ABI_VERSION */
+    int32_t flags;         /* reserved, 0 */
+    int64_t reserved[6];   /* 0 */
+} shs_config;
+
+typedef struct shs_info_t {
+    int64_t n, m, p;
+    double  reduce_ms;       /* device time of shs_reduce (HIP events) */
+    size_t  resident_bytes;  /* device memory the handle owns */
+} shs_info_t;
+
+/*
+ * Controller-Hessenberg reduction (Algorithm 1, Section 2; the reflector
+ * sequence of Section 2.1).
+ *
+ *   n, m, p   sizes: A is n x n, B is n x m, C is p x n; need 1 <= m <= SHS_MAX_M,
+ *             m < n, p >= 0.
+ *   A, B, C   column-major FP64 device arrays with leading dimensions lda >= n,
+ *             ldb >= n, ldc >= max(1, p); read only; C may be NULL if p == 0.
+ *   cfg       NULL for defaults, else abi_version must equal SHS_ABI_VERSION.
+ *   stream    HIP stream the reduction runs on.
+ *   out       receives a new handle.
+ *
+ * The call is synchronous with respect to `stream` (it returns after the
+ * reduction has finished).  The handle owns device copies of H, R, Ct, the
+ * Householder vectors of Q, an FP32 copy of H and the off-diagonal row sums
+ * of H; release it with shs_destroy.  The reduced form is sign-normalised:
+ * R(i,i) >= 0 and H(j+m, j) >= 0.  Errors: -1..-13 for bad arguments,
+ * SHS_ERR_NOMEM, SHS_ERR_HIP.
+ */
+int shs_reduce(int64_t n, int64_t m, int64_t p,
+               const double *A, int64_t lda,
+               const double *B, int64_t ldb,
+               const double *C, int64_t ldc,
+               const shs_config *cfg, void *stream, shs_handle **out);
+
+/*
+ * Exact number of bytes of device workspace shs_solve needs for `s` shifts
+ * with the given mode and outputs (per-shift reflector store, the FP32
+ * buffers of the mixed path, residual and bookkeeping).  The serving layer
+ * admits work by this figure.
+ */
+int shs_solve_workspace(const shs_handle *h, int64_t s, int mode, int outputs,
+                        size_t *bytes);
+
+/*
+ * Solve (H - sigma_j I) X_j = R and form G_j = Ct X_j for j = 0..s-1.
+ *
+ *   shifts     device, s complex values (interleaved re, im).
+ *   mode       SHS_MODE_FP64 or SHS_MODE_FP32_REFINE.
+ *   outputs    OR of SHS_OUT_X, SHS_OUT_G, SHS_OUT_ETA (at least X or G).
+ *   tol        backward-error target of the mixed mode (e.g. 1e-13); ignored
+ *              by SHS_MODE_FP64.
+ *   max_iter   refinement iterations before falling back to FP64 (mixed mode).
+ *   work       device workspace of work_bytes >= shs_solve_workspace(...), or
+ *              NULL to let the library allocate it on `stream` (stream-ordered).
+ *   X, ldx     device, n x (s*m) complex, X(:, j*m:(j+1)*m) = X_j in reduced
+ *              coordinates (multiply by Q, shs_apply_q, for A's coordinates);
+ *              required when SHS_OUT_X is set, else may be NULL.
+ *   G, ldg     device, p x (s*m) complex, G(:, j*m:(j+1)*m) = G_j; required
+ *              when SHS_OUT_G is set and p > 0.
+ *   eta        device, s doubles, the normwise backward error
+ *              max_c ||r_c||_inf / (||H - sigma I||_inf ||x_c||_inf + ||R(:,c)||_inf)
+ *              with r = R - (H X_j - sigma_j X_j) evaluated in FP64; required
+ *              when SHS_OUT_ETA is set or the mode is mixed.
+ *   status     device, s int32 SHS_STATUS_* codes, always written.  A bad
+ *              shift never fails the call; its outputs are NaN.
+ *
+ * Asynchronous on `stream` except in mixed mode, which synchronises the
+ * stream between refinement iterations to decide which shifts continue.
+ * One solve per handle at a time per stream.
+ */
+int shs_solve(shs_handle *h, int64_t s, const double *shifts,
+              int mode, int outputs, double tol, int max_iter,
+              void *work, size_t work_bytes,
+              double *X, int64_t ldx, double *G, int64_t ldg,
+              double *eta, int32_t *status, void *stream);
+
+/*
+ * X_orig = Q X_red: maps ncols reduced-coordinate columns (complex, device,
+ * n x ncols, leading dimension ld) to A's coordinates (device, ldo), where
+ * X_orig = (A - sigma I)^{-1} B for a solution X_red of the reduced system
+ * (Section 2: the change of coordinates is orthogonal).  Xred and Xorig may
+ * be the same array when ld == ldo.  Asynchronous on `stream`.
+ */
+int shs_apply_q(const shs_handle *h, int64_t ncols,
+                const double *Xred, int64_t ld, double *Xorig, int64_t ldo,
+                void *stream);
+
+/*
+ * Copy the reduced form to caller device arrays (column-major FP64):
+ * H n x n (ldh >= n), R n x m (ldr >= n; rows >= m are zero), Ct p x n
+ * (ldct >= max(1,p)); any pointer may be NULL to skip it.  Asynchronous.
+ */
+int shs_get_reduced(const shs_handle *h, double *H, int64_t ldh,
+                    double *R, int64_t ldr, double *Ct, int64_t ldct,
+                    void *stream);
+
+/* Sizes, reduction time and resident bytes of a handle. */
+int shs_info(const shs_handle *h, shs_info_t *info);
+
+/*
+ * Phase timing of the most recent shs_solve on a handle.  When enabled with
+ * shs_set_timing(h, 1), shs_solve records HIP events on its stream around
+ * every kernel phase; shs_last_timings waits for the last of them and sums
+ * the elapsed device time per phase (milliseconds).  Calls per phase are
+ * counted in the *_calls fields.  Disabled by default (no events recorded).
+ */
+typedef struct shs_timings_t {
+    double sweep_ms;          /* FP64 sweep (structured right-hand side) */
+    double qstar_ms;          /* Q* passes (all precisions) */
+    double residual_ms;       /* FP64 residual GEMM + backward error */
+    double sweep32_ms;        /* FP32 sweep, structured right-hand side */
+    double sweep32_dense_ms;  /* FP32 correction sweeps (dense right-hand side) */
+    double other_ms;          /* G evaluation, scaling, bookkeeping */
+    int64_t sweep_calls, qstar_calls, residual_calls, sweep32_calls, sweep32_dense_calls, other_calls;
+    int64_t sweep_shifts;     /* shifts processed by FP64 sweeps */
+    int64_t sweep32_shifts;   /* shifts processed by FP32 structured sweeps */
+    int64_t sweep32_dense_shifts; /* shift-solves processed by FP32 dense sweeps */
+    int64_t refine_iterations;    /* correction rounds run by the mixed mode */
+    int64_t fallback_shifts;      /* shifts the mixed mode recomputed in FP64 */
+} shs_timings_t;
+
+int shs_set_timing(shs_handle *h, int enable);
+int shs_last_timings(const shs_handle *h, shs_timings_t *out);
+
+/* Release a handle and all device memory it owns (synchronises its device). */
+void shs_destroy(shs_handle *h);
+
+/* Static text for any return code of this library. */
+const char *shs_strerror(int code);
+
+/* ABI version compiled into the library (SHS_ABI_VERSION). */
+int shs_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHIFTSOLVE_H */

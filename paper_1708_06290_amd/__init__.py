@@ -1,0 +1,116 @@
+"""Many shifted linear systems on one MI355X: (A - sigma_j I) X_j = B, G_j = C X_j.
+
+A thin Python layer over ``libshiftsolve.so`` (C ABI in ``include/shiftsolve.h``):
+PyTorch provides device memory and streams, the HIP kernels do all the work.
+
+    sys = System(A, B, C)                 # controller-Hessenberg reduction (once)
+    res = sys.solve(shifts)               # X (reduced coordinates), G, eta, status
+    Xa = sys.apply_q(res.X)               # back to A's coordinates
+
+G_j = C (A - sigma_j I)^{-1} B, which is minus the transfer function
+C (sigma I - A)^{-1} B of the paper's notation.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+from ._lib import (SHS_MAX_M, SHS_MODE_FP32_REFINE, SHS_MODE_FP64, SHS_OUT_ETA, SHS_OUT_G, SHS_OUT_X,
+                   SHS_STATUS_FALLBACK, SHS_STATUS_NONFINITE, SHS_STATUS_NOT_CONVERGED, SHS_STATUS_OK,
+                   SHS_STATUS_SINGULAR, ShsError, library, shs_apply_q, shs_destroy, shs_get_reduced,
+                   shs_info, shs_last_timings, shs_reduce, shs_set_timing, shs_solve, shs_solve_workspace)
+
+__all__ = ["System", "SolveResult", "library", "shs_reduce", "shs_solve", "shs_solve_workspace",
+           "shs_apply_q", "shs_get_reduced", "shs_info", "shs_set_timing", "shs_last_timings",
+           "shs_destroy", "ShsError",
+           "SHS_MODE_FP64", "SHS_MODE_FP32_REFINE", "SHS_OUT_X", "SHS_OUT_G", "SHS_OUT_ETA",
+           "SHS_STATUS_OK", "SHS_STATUS_SINGULAR", "SHS_STATUS_NONFINITE", "SHS_STATUS_FALLBACK",
+           "SHS_STATUS_NOT_CONVERGED", "SHS_MAX_M"]
+
+
+@dataclasses.dataclass
+class SolveResult:
+    X: object        # (n, s*m) complex128 view (column-major storage), or None
+    G: object        # (p, s*m) complex128 view, or None
+    eta: object      # (s,) float64, or None
+    status: object   # (s,) int32
+
+
+class System:
+    """A reduced system resident on the current GPU."""
+
+    def __init__(self, A, B, C, stream=None):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        A = torch.as_tensor(A, dtype=torch.float64, device=dev)
+        B = torch.as_tensor(B, dtype=torch.float64, device=dev)
+        C = torch.as_tensor(C, dtype=torch.float64, device=dev)
+        if B.dim() == 1:
+            B = B[:, None]
+        if C.dim() == 1:
+            C = C[None, :]
+        self.n, self.m = B.shape
+        self.p = C.shape[0]
+        self.device = dev
+        self.handle = shs_reduce(A, B, C, stream)
+
+    def close(self):
+        if self.handle is not None:
+            shs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        return shs_info(self.handle)
+
+    def set_timing(self, enable=True):
+        shs_set_timing(self.handle, enable)
+
+    def last_timings(self):
+        return shs_last_timings(self.handle)
+
+    def reduced(self, stream=None):
+        """(H, R, Ct) as (n, n), (n, m), (p, n) float64 tensors."""
+        import torch
+        H = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+        R = torch.empty((self.m, self.n), dtype=torch.float64, device=self.device)
+        Ct = torch.empty((self.n, max(1, self.p)), dtype=torch.float64, device=self.device)
+        shs_get_reduced(self.handle, H, R, Ct, stream)
+        return H.t(), R.t(), Ct.t()[: self.p]
+
+    def workspace_bytes(self, s, mode=SHS_MODE_FP64, outputs=SHS_OUT_X | SHS_OUT_G):
+        return shs_solve_workspace(self.handle, s, mode, outputs)
+
+    def solve(self, shifts, mode=SHS_MODE_FP64, outputs=SHS_OUT_X | SHS_OUT_G | SHS_OUT_ETA,
+              tol=1e-13, max_iter=5, work=None, stream=None, out=None):
+        """Solve for every shift; returns a :class:`SolveResult` (tensors on the GPU)."""
+        import torch
+        shifts = torch.as_tensor(shifts, dtype=torch.complex128, device=self.device).reshape(-1).contiguous()
+        s = shifts.numel()
+        n, m, p = self.n, self.m, self.p
+        if out is not None:
+            Xs, Gs, eta, status = out
+        else:
+            Xs = torch.empty((s * m, n), dtype=torch.complex128, device=self.device) if outputs & SHS_OUT_X else None
+            Gs = (torch.empty((s * m, max(1, p)), dtype=torch.complex128, device=self.device)
+                  if (outputs & SHS_OUT_G) and p > 0 else None)
+            need_eta = (outputs & SHS_OUT_ETA) or mode == SHS_MODE_FP32_REFINE
+            eta = torch.empty(s, dtype=torch.float64, device=self.device) if need_eta else None
+            status = torch.empty(s, dtype=torch.int32, device=self.device)
+        shs_solve(self.handle, shifts, Xs, Gs, eta, status, mode=mode, outputs=outputs, tol=tol,
+                  max_iter=max_iter, work=work, stream=stream)
+        X = Xs.t() if Xs is not None else None
+        G = Gs.t()[:p] if Gs is not None else None
+        return SolveResult(X, G, eta, status)
+
+    def apply_q(self, X, stream=None):
+        """Q X for an (n, k) complex128 tensor of reduced-coordinate columns."""
+        import torch
+        Xs = X.t().contiguous()
+        out = torch.empty_like(Xs)
+        shs_apply_q(self.handle, Xs, out, stream)
+        return out.t()

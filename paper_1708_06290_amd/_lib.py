@@ -1,0 +1,215 @@
+"""ctypes binding of libshiftsolve.so -- argument marshalling only.
+
+Every function here converts torch tensors to pointers and calls the C ABI
+declared in ``include/shiftsolve.h``; all arithmetic happens in the HIP
+kernels.  There is no fallback: if the library is missing, or the tensors
+are not on the GPU, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshiftsolve.so")
+
+SHS_ABI_VERSION = 1
+SHS_MODE_FP64 = 0
+SHS_MODE_FP32_REFINE = 1
+SHS_OUT_X = 1
+SHS_OUT_G = 2
+SHS_OUT_ETA = 4
+SHS_STATUS_OK = 0
+SHS_STATUS_SINGULAR = 1
+SHS_STATUS_NONFINITE = 2
+SHS_STATUS_FALLBACK = 3
+SHS_STATUS_NOT_CONVERGED = 4
+SHS_MAX_M = 16
+
+EXPORTED = ("shs_reduce", "shs_solve_workspace", "shs_solve", "shs_apply_q", "shs_get_reduced",
+            "shs_info", "shs_set_timing", "shs_last_timings", "shs_destroy", "shs_strerror",
+            "shs_abi_version")
+
+_lib = None
+
+
+class ShsError(RuntimeError):
+    def __init__(self, func: str, code: int):
+        self.code = code
+        msg = _load().shs_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{func} failed with code {code}: {msg}")
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("p", ctypes.c_int64),
+                ("reduce_ms", ctypes.c_double), ("resident_bytes", ctypes.c_size_t)]
+
+
+class _Timings(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double) for f in ("sweep_ms", "qstar_ms", "residual_ms", "sweep32_ms",
+                                               "sweep32_dense_ms", "other_ms")] + \
+               [(f, ctypes.c_int64) for f in ("sweep_calls", "qstar_calls", "residual_calls", "sweep32_calls",
+                                              "sweep32_dense_calls", "other_calls", "sweep_shifts",
+                                              "sweep32_shifts", "sweep32_dense_shifts", "refine_iterations",
+                                              "fallback_shifts")]
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int64 * 6)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_1708_06290_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64, vp, dp = ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p
+    lib.shs_reduce.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64, ctypes.POINTER(_Config), vp,
+                               ctypes.POINTER(vp)]
+    lib.shs_reduce.restype = ctypes.c_int
+    lib.shs_solve_workspace.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    lib.shs_solve_workspace.restype = ctypes.c_int
+    lib.shs_solve.argtypes = [vp, i64, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                              vp, ctypes.c_size_t, dp, i64, dp, i64, dp, vp, vp]
+    lib.shs_solve.restype = ctypes.c_int
+    lib.shs_apply_q.argtypes = [vp, i64, dp, i64, dp, i64, vp]
+    lib.shs_apply_q.restype = ctypes.c_int
+    lib.shs_get_reduced.argtypes = [vp, dp, i64, dp, i64, dp, i64, vp]
+    lib.shs_get_reduced.restype = ctypes.c_int
+    lib.shs_info.argtypes = [vp, ctypes.POINTER(_Info)]
+    lib.shs_info.restype = ctypes.c_int
+    lib.shs_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.shs_set_timing.restype = ctypes.c_int
+    lib.shs_last_timings.argtypes = [vp, ctypes.POINTER(_Timings)]
+    lib.shs_last_timings.restype = ctypes.c_int
+    lib.shs_destroy.argtypes = [vp]
+    lib.shs_destroy.restype = None
+    lib.shs_strerror.argtypes = [ctypes.c_int]
+    lib.shs_strerror.restype = ctypes.c_char_p
+    lib.shs_abi_version.argtypes = []
+    lib.shs_abi_version.restype = ctypes.c_int
+    if lib.shs_abi_version() != SHS_ABI_VERSION:
+        raise RuntimeError("libshiftsolve ABI version mismatch")
+    _lib = lib
+    return lib
+
+
+def library():
+    """The loaded ctypes library (raises if it is not built)."""
+    return _load()
+
+
+def _check(func: str, rc: int):
+    if rc != 0:
+        raise ShsError(func, rc)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _colmajor(t):
+    """Column-major copy of a 2-D tensor: returns (storage tensor, ld)."""
+    if t.dim() == 1:
+        t = t[:, None]
+    cm = t.t().contiguous()          # row-major of t^T == column-major of t
+    return cm, t.shape[0]
+
+
+def shs_reduce(A, B, C, stream=None):
+    """Controller-Hessenberg reduction of (A, B, C) (float64 CUDA tensors); returns a handle."""
+    import torch
+    lib = _load()
+    for name, t in (("A", A), ("B", B), ("C", C)):
+        if not (t.is_cuda and t.dtype == torch.float64):
+            raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if B.dim() == 1:
+        B = B[:, None]
+    if C.dim() == 1:
+        C = C[None, :]
+    n, m = B.shape
+    p = C.shape[0]
+    Ac, lda = _colmajor(A)
+    Bc, ldb = _colmajor(B)
+    Cc, ldc = _colmajor(C) if p > 0 else (None, 1)
+    cfg = _Config(abi_version=SHS_ABI_VERSION)
+    h = ctypes.c_void_p()
+    rc = lib.shs_reduce(n, m, p, _ptr(Ac), lda, _ptr(Bc), ldb, _ptr(Cc), max(1, ldc), ctypes.byref(cfg),
+                        _stream(stream), ctypes.byref(h))
+    _check("shs_reduce", rc)
+    return h
+
+
+def shs_solve_workspace(h, s, mode, outputs):
+    lib = _load()
+    b = ctypes.c_size_t()
+    _check("shs_solve_workspace", lib.shs_solve_workspace(h, s, mode, outputs, ctypes.byref(b)))
+    return b.value
+
+
+def shs_solve(h, shifts, X, G, eta, status, mode=SHS_MODE_FP64, outputs=SHS_OUT_X | SHS_OUT_G,
+              tol=1e-13, max_iter=5, work=None, stream=None):
+    """Raw solve: every array is a caller-allocated CUDA tensor (see shiftsolve.h).
+
+    ``X`` is a (s*m, n) complex128 tensor (column-major n x (s*m)), ``G`` a
+    (s*m, p) complex128 tensor, ``eta`` (s,) float64, ``status`` (s,) int32,
+    ``shifts`` (s,) complex128.
+    """
+    lib = _load()
+    s = shifts.numel()
+    ldx = X.shape[1] if X is not None else 1
+    ldg = G.shape[1] if G is not None else 1
+    wptr, wbytes = (_ptr(work), work.numel() * work.element_size()) if work is not None else (None, 0)
+    rc = lib.shs_solve(h, s, _ptr(shifts), mode, outputs, tol, max_iter, wptr, wbytes,
+                       _ptr(X), ldx, _ptr(G), ldg, _ptr(eta), _ptr(status), _stream(stream))
+    _check("shs_solve", rc)
+
+
+def shs_apply_q(h, Xred, Xorig, stream=None):
+    """Xorig = Q Xred for (ncols, n) complex128 tensors (column-major n x ncols)."""
+    lib = _load()
+    ncols, n = Xred.shape
+    _check("shs_apply_q", lib.shs_apply_q(h, ncols, _ptr(Xred), n, _ptr(Xorig), Xorig.shape[1],
+                                          _stream(stream)))
+
+
+def shs_get_reduced(h, H, R, Ct, stream=None):
+    """Copy H (n, n), R (m, n), Ct (n, p) -- transposed storage of column-major arrays."""
+    lib = _load()
+    _check("shs_get_reduced", lib.shs_get_reduced(h, _ptr(H), H.shape[1] if H is not None else 1,
+                                                  _ptr(R), R.shape[1] if R is not None else 1,
+                                                  _ptr(Ct), Ct.shape[1] if Ct is not None else 1,
+                                                  _stream(stream)))
+
+
+def shs_info(h):
+    lib = _load()
+    info = _Info()
+    _check("shs_info", lib.shs_info(h, ctypes.byref(info)))
+    return {"n": info.n, "m": info.m, "p": info.p, "reduce_ms": info.reduce_ms,
+            "resident_bytes": info.resident_bytes}
+
+
+def shs_set_timing(h, enable: bool):
+    _check("shs_set_timing", _load().shs_set_timing(h, 1 if enable else 0))
+
+
+def shs_last_timings(h):
+    """Per-phase device time (ms) and counters of the last solve on the handle."""
+    t = _Timings()
+    _check("shs_last_timings", _load().shs_last_timings(h, ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in _Timings._fields_}
+
+
+def shs_destroy(h):
+    _load().shs_destroy(h)

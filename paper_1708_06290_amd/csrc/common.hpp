@@ -1,0 +1,64 @@
+// Shared device/host helpers of the shiftsolve library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+namespace shs {
+
+constexpr int kWave = 64;
+
+// Per-shift reflector-store slot, in elements of the sweep precision:
+//   [tau, pad, v_0.re, v_0.im, ..., v_{m-1}.re, v_{m-1}.im]            structured
+//   [..., y_0.re, y_0.im, ..., y_{m-1}.re, y_{m-1}.im]                  + dense RHS
+// The implicit last entry v_m of every reflector is 1.
+__host__ __device__ constexpr int slot_elems(int m, bool dense) { return 2 + 2 * m + (dense ? 2 * m : 0); }
+
+// Rows of the window a lane keeps in registers: the state of one row is
+// 2(m+1) values (+2m for a dense right-hand side); the budget keeps the
+// kernel near 200 VGPRs so that two waves fit on each SIMD.
+template <typename T, int M, bool DENSE>
+__host__ __device__ constexpr int rows_per_lane()
+{
+    constexpr int vals = 2 * (M + 1) + (DENSE ? 2 * M : 0);
+    constexpr int vgprs = vals * (int)(sizeof(T) / 4);
+    constexpr int r = 144 / vgprs;
+    return r < 1 ? 1 : (r > 8 ? 8 : r);
+}
+
+__device__ inline double readlane(double x, int lane)
+{
+    int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline float readlane(float x, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+
+template <typename T> __device__ inline T dsqrt(T x);
+template <> __device__ inline double dsqrt<double>(double x) { return sqrt(x); }
+template <> __device__ inline float dsqrt<float>(float x) { return sqrtf(x); }
+
+// Non-negative doubles order like their bit patterns, which lets an
+// unsigned 64-bit atomic max act as a floating-point max.
+__device__ inline void atomic_max_nonneg(unsigned long long *addr, double v)
+{
+    atomicMax(addr, (unsigned long long)__double_as_longlong(v));
+}
+
+}  // namespace shs
+
+#define SHS_HIP_CHECK(expr)                                                      \
+    do {                                                                         \
+        hipError_t e_ = (expr);                                                  \
+        if (e_ != hipSuccess) {                                                  \
+            fprintf(stderr, "shiftsolve: %s failed: %s (%s:%d)\n", #expr,        \
+                    hipGetErrorString(e_), __FILE__, __LINE__);                  \
+            return SHS_ERR_HIP;                                                  \
+        }                                                                        \
+    } while (0)

@@ -1,0 +1,63 @@
+// Instantiates the sweep and Q* kernels for precision REAL_T and the m values
+// M_FIRST..M_LAST, with launcher names suffixed SUFFIX.
+#include "kernels.hpp"
+
+namespace shs {
+
+template <int MM>
+struct Inst {
+    static void geometry(bool dense, SweepGeometry *g)
+    {
+        if (dense) {
+            g->rows_per_lane = rows_per_lane<REAL_T, MM, true>();
+            g->slot = slot_elems(MM, true);
+        } else {
+            g->rows_per_lane = rows_per_lane<REAL_T, MM, false>();
+            g->slot = slot_elems(MM, false);
+        }
+        g->tile_rows = kWave * g->rows_per_lane;
+        g->tile_stride = refl_tile_stride<REAL_T>(g->tile_rows, g->slot);
+    }
+    static void sweep(bool dense, const SweepArgs<REAL_T> &a, hipStream_t st)
+    {
+        if (dense)
+            hipLaunchKernelGGL((sweep_kernel<REAL_T, MM, true>), dim3(a.count), dim3(kWave), 0, st, a);
+        else
+            hipLaunchKernelGGL((sweep_kernel<REAL_T, MM, false>), dim3(a.count), dim3(kWave), 0, st, a);
+    }
+    static void qstar(bool dense_in, const QstarArgs<REAL_T> &a, hipStream_t st)
+    {
+        constexpr int spw = kWave / MM;
+        const int blocks = (a.count + spw - 1) / spw;
+        if (dense_in)
+            hipLaunchKernelGGL((qstar_kernel<REAL_T, MM, true>), dim3(blocks), dim3(kWave), 0, st, a);
+        else
+            hipLaunchKernelGGL((qstar_kernel<REAL_T, MM, false>), dim3(blocks), dim3(kWave), 0, st, a);
+    }
+};
+
+#define SHS_CAT3_(a, b, c) a##b##c
+#define SHS_CAT3(a, b, c) SHS_CAT3_(a, b, c)
+
+bool SHS_CAT3(sweep_geometry_, SUFFIX, PART)(int m, bool dense, SweepGeometry *g)
+{
+    bool ok = false;
+    SHS_DISPATCH_M(m, if constexpr (MM >= M_FIRST && MM <= M_LAST) { Inst<MM>::geometry(dense, g); ok = true; });
+    return ok;
+}
+
+bool SHS_CAT3(launch_sweep_, SUFFIX, PART)(int m, bool dense, const SweepArgs<REAL_T> &a, hipStream_t st)
+{
+    bool ok = false;
+    SHS_DISPATCH_M(m, if constexpr (MM >= M_FIRST && MM <= M_LAST) { Inst<MM>::sweep(dense, a, st); ok = true; });
+    return ok;
+}
+
+bool SHS_CAT3(launch_qstar_, SUFFIX, PART)(int m, bool dense_in, const QstarArgs<REAL_T> &a, hipStream_t st)
+{
+    bool ok = false;
+    SHS_DISPATCH_M(m, if constexpr (MM >= M_FIRST && MM <= M_LAST) { Inst<MM>::qstar(dense_in, a, st); ok = true; });
+    return ok;
+}
+
+}  // namespace shs

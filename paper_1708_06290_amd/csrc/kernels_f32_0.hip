@@ -1,0 +1,7 @@
+// float instances of the sweep and Q* kernels for m = 1..3.
+#define REAL_T float
+#define SUFFIX f32
+#define PART _0
+#define M_FIRST 1
+#define M_LAST 3
+#include "inst_template.hpp"

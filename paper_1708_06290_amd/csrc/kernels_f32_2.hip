@@ -1,0 +1,7 @@
+// float instances of the sweep and Q* kernels for m = 7..9.
+#define REAL_T float
+#define SUFFIX f32
+#define PART _2
+#define M_FIRST 7
+#define M_LAST 9
+#include "inst_template.hpp"

@@ -1,0 +1,809 @@
+// C-ABI entry points of the shiftsolve library (declared in shiftsolve.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "shiftsolve.h"
+#include "kernels.hpp"
+#include "reduce.hpp"
+#include "residual.hpp"
+
+using namespace shs;
+
+struct shs_handle {
+    int64_t n = 0, m = 0, p = 0;
+    int device = 0;
+    int64_t ldh = 0;
+    double *H = nullptr;       // n x n, sign-normalised m-Hessenberg
+    float *H32 = nullptr;      // FP32 copy for the mixed-precision sweep
+    double *Bw = nullptr;      // n x m, R = Q^T B (rows >= m zero)
+    double *Rtop = nullptr;    // m x m leading block of R (ld m)
+    double *rcolmax = nullptr; // max_i |R(i, c)|
+    double *Ct = nullptr;      // p x n, C Q (ld max(1,p))
+    int64_t ldct = 1;
+    double *V = nullptr;       // Householder vectors: column j holds reflector j from row start[j]
+    double *tauv = nullptr;    // n taus (reflectors 0..m-1 of Q_B, then m.. of Q_A)
+    int64_t nrefl = 0;
+    double *sgn = nullptr;     // diagonal signs
+    double *offrow = nullptr;  // off-diagonal row sums of |H|
+    double *diag = nullptr;    // diagonal of H
+    double reduce_ms = 0.0;
+    size_t resident = 0;
+    // phase timing of the last solve (events recorded on the solve's stream)
+    bool timing = false;
+    struct Mark { int phase; int64_t shifts; hipEvent_t a, b; };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> pool;
+    int64_t refine_iterations = 0, fallback_shifts = 0;
+};
+
+enum { PH_SWEEP = 0, PH_QSTAR, PH_RESIDUAL, PH_SWEEP32, PH_SWEEP32D, PH_OTHER, PH_COUNT };
+
+namespace {
+
+template <typename T>
+hipError_t dmalloc(T **p, size_t count, size_t *acc)
+{
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * std::max<size_t>(count, 1));
+    if (e == hipSuccess && acc) *acc += sizeof(T) * std::max<size_t>(count, 1);
+    return e;
+}
+
+void free_handle(shs_handle *h)
+{
+    if (!h) return;
+    for (hipEvent_t ev : h->pool) hipEventDestroy(ev);
+    hipFree(h->H);
+    hipFree(h->H32);
+    hipFree(h->Bw);
+    hipFree(h->Rtop);
+    hipFree(h->rcolmax);
+    hipFree(h->Ct);
+    hipFree(h->V);
+    hipFree(h->tauv);
+    hipFree(h->sgn);
+    hipFree(h->offrow);
+    hipFree(h->diag);
+    delete h;
+}
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// Records an event pair around one phase when timing is enabled.
+struct PhaseScope {
+    shs_handle *h;
+    hipStream_t st;
+    int idx = -1;
+    PhaseScope(shs_handle *h_, int phase, int64_t shifts, hipStream_t st_) : h(h_), st(st_)
+    {
+        if (!h->timing) return;
+        const size_t need = 2 * (h->marks.size() + 1);
+        while (h->pool.size() < need) {
+            hipEvent_t ev;
+            if (hipEventCreate(&ev) != hipSuccess) return;
+            h->pool.push_back(ev);
+        }
+        shs_handle::Mark mk{phase, shifts, h->pool[2 * h->marks.size()], h->pool[2 * h->marks.size() + 1]};
+        hipEventRecord(mk.a, st);
+        idx = (int)h->marks.size();
+        h->marks.push_back(mk);
+    }
+    ~PhaseScope()
+    {
+        if (idx >= 0) hipEventRecord(h->marks[idx].b, st);
+    }
+};
+
+// start row of reflector idx (0..m-1: QR of B, j; m..: m-Hessenberg column j -> j + m)
+inline int64_t refl_start(int64_t m, int64_t idx) { return idx < m ? idx : (idx - m) + m; }
+
+// Apply reflector (v, tau) on rows [r0, r0 + L) from the left to columns
+// [c0, c1) of A and from the right to columns [r0, r0 + L) of the first
+// `rows` rows of A (two-sided), and from the right to Ct.
+hipError_t two_sided(shs_handle *h, double *A, int64_t lda, int64_t L, int64_t r0, int64_t c0,
+                     const double *v, const double *tau, double *part, hipStream_t st)
+{
+    const int64_t n = h->n;
+    const int nchunks = (int)cdiv(L, kRightChunk);
+    if (n - c0 > 0)
+        hipLaunchKernelGGL(left_update_kernel, dim3((unsigned)(n - c0)), dim3(256), 0, st, (int)L, (int)r0,
+                           (int)c0, A, lda, v, tau);
+    hipLaunchKernelGGL(right_dot_kernel, dim3(cdiv(n, 256), nchunks), dim3(256), 0, st, (int)n, (int)L,
+                       (int)r0, (const double *)A, lda, v, tau, part);
+    hipLaunchKernelGGL(right_update_kernel, dim3(cdiv(n, 256), nchunks), dim3(256), 0, st, (int)n, (int)L,
+                       (int)r0, A, lda, v, tau, (const double *)part, nchunks);
+    if (h->p > 0) {
+        hipLaunchKernelGGL(right_dot_kernel, dim3(cdiv(h->p, 256), nchunks), dim3(256), 0, st, (int)h->p,
+                           (int)L, (int)r0, (const double *)h->Ct, h->ldct, v, tau, part);
+        hipLaunchKernelGGL(right_update_kernel, dim3(cdiv(h->p, 256), nchunks), dim3(256), 0, st, (int)h->p,
+                           (int)L, (int)r0, h->Ct, h->ldct, v, tau, (const double *)part, nchunks);
+    }
+    return hipGetLastError();
+}
+
+struct Geo {
+    SweepGeometry g;
+    int64_t stride;   // elements per shift in the reflector store
+};
+
+bool geo(bool fp32, int64_t n, int64_t m, bool dense, Geo *out)
+{
+    if (!sweep_geometry(fp32, (int)m, dense, &out->g)) return false;
+    out->stride = out->g.refl_stride((int)n);
+    return true;
+}
+
+// Workspace layout (byte offsets, each 256-byte aligned).
+struct Layout {
+    size_t refl64 = 0, y64 = 0, x = 0, resmax = 0, xmax = 0, list = 0;
+    size_t refl32 = 0, y32 = 0, e32 = 0, yd32 = 0, res = 0, scale = 0, eta_prev = 0, status2 = 0;
+    size_t total = 0;
+};
+
+inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
+{
+    const int64_t n = h->n, m = h->m;
+    Geo g64, g32s, g32d;
+    if (!geo(false, n, m, false, &g64)) return false;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += al(bytes); return o; };
+    L->refl64 = take(sizeof(double) * g64.stride * s);
+    L->y64 = take(sizeof(double) * 2 * m * m * s);
+    L->x = (outputs & SHS_OUT_X) ? 0 : take(sizeof(double) * 2 * n * m * s);
+    L->resmax = take(sizeof(unsigned long long) * m * s);
+    L->xmax = take(sizeof(unsigned long long) * m * s);
+    L->list = take(sizeof(int32_t) * s);
+    L->status2 = take(sizeof(int32_t) * s);
+    if (mode == SHS_MODE_FP32_REFINE) {
+        if (!geo(true, n, m, false, &g32s) || !geo(true, n, m, true, &g32d)) return false;
+        L->refl32 = take(sizeof(float) * std::max(g32s.stride, g32d.stride) * s);
+        L->y32 = take(sizeof(float) * 2 * m * m * s);
+        L->e32 = take(sizeof(float) * 2 * n * m * s);
+        L->yd32 = take(sizeof(float) * 2 * n * m * s);
+        L->res = take(sizeof(double) * 2 * n * m * s);
+        L->scale = take(sizeof(double) * s);
+        L->eta_prev = take(sizeof(double) * s);
+    }
+    L->total = off;
+    return true;
+}
+
+template <typename T>
+inline T *at(void *base, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(base) + off); }
+
+// E32(:, sid*m + c) = Res(:, sid*m + c) / scale[sid], scale = 2^ceil(log2(max |Res_sid|)).
+__global__ __launch_bounds__(256) void scale_residual_kernel(int n, int m, int count, const int32_t *list,
+                                                             const double *Res, const unsigned long long *resmax,
+                                                             double *scale, float *E32)
+{
+    const int item = blockIdx.y;
+    if (item >= count) return;
+    const int sid = list[item];
+    double mx = 0.0;
+    for (int c = 0; c < m; ++c) {
+        const double v = __longlong_as_double((long long)resmax[(int64_t)sid * m + c]);
+        mx = v > mx ? v : mx;
+    }
+    const double sc = mx > 0.0 ? exp2(ceil(log2(mx))) : 1.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) scale[sid] = sc;
+    const double inv = 1.0 / sc;
+    const int64_t total = (int64_t)n * m;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
+        const int64_t c = idx / n, i = idx % n;
+        const double *pr = Res + (((int64_t)sid * m + c) * n + i) * 2;
+        float *pe = E32 + ((int64_t)sid * n * m + c * n + i) * 2;
+        pe[0] = (float)(pr[0] * inv);
+        pe[1] = (float)(pr[1] * inv);
+    }
+}
+
+__global__ void fill_status_kernel(int count, const int32_t *list, const int32_t *src, int32_t *dst, int code)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const int sid = list ? list[i] : i;
+    const int st = src[sid];
+    dst[sid] = (st == 0) ? code : st;
+}
+
+// residual + eta for the listed shifts; Res optional.
+hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const double *shifts, const double *X,
+                   int64_t ldx, double *Res, unsigned long long *resmax, unsigned long long *xmax, double *eta,
+                   int32_t *status, int64_t s_total, hipStream_t st)
+{
+    const int64_t n = h->n, m = h->m;
+    PhaseScope ps(h, PH_RESIDUAL, s_list, st);
+    hipError_t e = hipMemsetAsync(resmax, 0, sizeof(unsigned long long) * m * s_total, st);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(xmax, 0, sizeof(unsigned long long) * m * s_total, st);
+    if (e != hipSuccess) return e;
+    ResidualArgs ra;
+    ra.n = (int)n;
+    ra.m = (int)m;
+    ra.count = (int)s_list;
+    ra.list = dlist;
+    ra.H = h->H;
+    ra.ldh = h->ldh;
+    ra.Rtop = h->Rtop;
+    ra.shifts = shifts;
+    ra.X = X;
+    ra.ldx = ldx;
+    ra.Res = Res;
+    ra.ldr = n;
+    ra.resmax = resmax;
+    ra.xmax = xmax;
+    hipLaunchKernelGGL(residual_kernel, dim3(cdiv(n, 64), cdiv(s_list * m, 32)), dim3(256), 0, st, ra);
+    hipLaunchKernelGGL(eta_kernel, dim3((unsigned)s_list), dim3(256), 0, st, (int)n, (int)m, (int)s_list, dlist,
+                       shifts, (const double *)h->offrow, (const double *)h->diag, (const double *)h->rcolmax,
+                       (const unsigned long long *)resmax, (const unsigned long long *)xmax, eta, status);
+    return hipGetLastError();
+}
+
+// FP64 sweep + Q* pass for the listed shifts into X.
+hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const double *shifts, void *work,
+                      const Layout &L, double *X, int64_t ldx, int32_t *status, hipStream_t st)
+{
+    const int64_t n = h->n, m = h->m;
+    Geo g;
+    geo(false, n, m, false, &g);
+    SweepArgs<double> sa{};
+    sa.n = (int)n;
+    sa.count = (int)count;
+    sa.H = h->H;
+    sa.ldh = h->ldh;
+    sa.shifts = shifts;
+    sa.list = dlist;
+    sa.Rtop = h->Rtop;
+    sa.refl = at<double>(work, L.refl64);
+    sa.refl_stride = g.stride;
+    sa.Y = at<double>(work, L.y64);
+    sa.y_stride = 2 * m * m;
+    sa.status = status;
+    {
+        PhaseScope ps(h, PH_SWEEP, count, st);
+        if (!launch_sweep((int)m, false, sa, st)) return hipErrorInvalidValue;
+    }
+    QstarArgs<double> qa{};
+    qa.n = (int)n;
+    qa.count = (int)count;
+    qa.list = dlist;
+    qa.refl = sa.refl;
+    qa.refl_stride = g.stride;
+    qa.tile_rows = g.g.tile_rows;
+    qa.tile_stride = g.g.tile_stride;
+    qa.slot = g.g.slot;
+    qa.Y = sa.Y;
+    qa.y_stride = 2 * m * m;
+    qa.X = X;
+    qa.ldx = ldx;
+    qa.accumulate = 0;
+    qa.scale = nullptr;
+    {
+        PhaseScope ps(h, PH_QSTAR, count, st);
+        if (!launch_qstar((int)m, false, qa, st)) return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+namespace shs {
+
+bool sweep_geometry(bool fp32, int m, bool dense, SweepGeometry *g)
+{
+    if (fp32)
+        return sweep_geometry_f32_0(m, dense, g) || sweep_geometry_f32_1(m, dense, g) ||
+               sweep_geometry_f32_2(m, dense, g) || sweep_geometry_f32_3(m, dense, g) ||
+               sweep_geometry_f32_4(m, dense, g) || sweep_geometry_f32_5(m, dense, g);
+    return sweep_geometry_f64_0(m, dense, g) || sweep_geometry_f64_1(m, dense, g) ||
+           sweep_geometry_f64_2(m, dense, g) || sweep_geometry_f64_3(m, dense, g) ||
+           sweep_geometry_f64_4(m, dense, g) || sweep_geometry_f64_5(m, dense, g);
+}
+
+bool launch_sweep(int m, bool dense, const SweepArgs<double> &a, hipStream_t st)
+{
+    return launch_sweep_f64_0(m, dense, a, st) || launch_sweep_f64_1(m, dense, a, st) ||
+           launch_sweep_f64_2(m, dense, a, st) || launch_sweep_f64_3(m, dense, a, st) ||
+           launch_sweep_f64_4(m, dense, a, st) || launch_sweep_f64_5(m, dense, a, st);
+}
+
+bool launch_sweep(int m, bool dense, const SweepArgs<float> &a, hipStream_t st)
+{
+    return launch_sweep_f32_0(m, dense, a, st) || launch_sweep_f32_1(m, dense, a, st) ||
+           launch_sweep_f32_2(m, dense, a, st) || launch_sweep_f32_3(m, dense, a, st) ||
+           launch_sweep_f32_4(m, dense, a, st) || launch_sweep_f32_5(m, dense, a, st);
+}
+
+bool launch_qstar(int m, bool dense_in, const QstarArgs<double> &a, hipStream_t st)
+{
+    return launch_qstar_f64_0(m, dense_in, a, st) || launch_qstar_f64_1(m, dense_in, a, st) ||
+           launch_qstar_f64_2(m, dense_in, a, st) || launch_qstar_f64_3(m, dense_in, a, st) ||
+           launch_qstar_f64_4(m, dense_in, a, st) || launch_qstar_f64_5(m, dense_in, a, st);
+}
+
+bool launch_qstar(int m, bool dense_in, const QstarArgs<float> &a, hipStream_t st)
+{
+    return launch_qstar_f32_0(m, dense_in, a, st) || launch_qstar_f32_1(m, dense_in, a, st) ||
+           launch_qstar_f32_2(m, dense_in, a, st) || launch_qstar_f32_3(m, dense_in, a, st) ||
+           launch_qstar_f32_4(m, dense_in, a, st) || launch_qstar_f32_5(m, dense_in, a, st);
+}
+
+}  // namespace shs
+
+#define RETURN_IF_HIP(expr)                                        \
+    do {                                                           \
+        hipError_t e_ = (expr);                                    \
+        if (e_ != hipSuccess) {                                    \
+            if (e_ == hipErrorOutOfMemory) return SHS_ERR_NOMEM;   \
+            return SHS_ERR_HIP;                                    \
+        }                                                          \
+    } while (0)
+
+extern "C" {
+
+int shs_abi_version(void) { return SHS_ABI_VERSION; }
+
+const char *shs_strerror(int code)
+{
+    if (code < 0) return "invalid argument";
+    switch (code) {
+    case 0: return "success";
+    case SHS_ERR_NOMEM: return "out of device memory or over budget";
+    case SHS_ERR_HIP: return "HIP runtime error";
+    case SHS_ERR_UNSUPPORTED: return "unsupported shape";
+    case SHS_ERR_BUSY: return "busy";
+    case SHS_ERR_NOTFOUND: return "unknown id";
+    case SHS_ERR_TIMEOUT: return "timed out";
+    default: return "unknown error";
+    }
+}
+
+int shs_reduce(int64_t n, int64_t m, int64_t p, const double *A, int64_t lda, const double *B, int64_t ldb,
+               const double *C, int64_t ldc, const shs_config *cfg, void *stream, shs_handle **out)
+{
+    if (n < 2) return -1;
+    if (m < 1 || m >= n) return -2;
+    if (m > SHS_MAX_M) return SHS_ERR_UNSUPPORTED;
+    if (p < 0) return -3;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (!B) return -6;
+    if (ldb < n) return -7;
+    if (p > 0 && !C) return -8;
+    if (ldc < std::max<int64_t>(1, p)) return -9;
+    if (cfg && cfg->abi_version != SHS_ABI_VERSION) return -10;
+    if (!out) return -12;
+    if (n > (int64_t)INT32_MAX / 2) return SHS_ERR_UNSUPPORTED;
+    *out = nullptr;
+    hipStream_t st = (hipStream_t)stream;
+
+    shs_handle *h = new (std::nothrow) shs_handle();
+    if (!h) return SHS_ERR_NOMEM;
+    h->n = n;
+    h->m = m;
+    h->p = p;
+    hipGetDevice(&h->device);
+    h->ldh = n;
+    h->ldct = std::max<int64_t>(1, p);
+    h->nrefl = m + std::max<int64_t>(0, n - m - 1);
+    size_t acc = 0;
+    hipError_t e = hipSuccess;
+    double *part = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+#define ALLOC(ptr, cnt)                                \
+    do {                                               \
+        e = dmalloc(&(ptr), (size_t)(cnt), &acc);      \
+        if (e != hipSuccess) goto fail;                \
+    } while (0)
+    ALLOC(h->H, n * n);
+    ALLOC(h->H32, n * n);
+    ALLOC(h->Bw, n * m);
+    ALLOC(h->Rtop, m * m);
+    ALLOC(h->rcolmax, m);
+    ALLOC(h->Ct, h->ldct * n);
+    ALLOC(h->V, n * h->nrefl);
+    ALLOC(h->tauv, h->nrefl);
+    ALLOC(h->sgn, n);
+    ALLOC(h->offrow, n);
+    ALLOC(h->diag, n);
+#undef ALLOC
+    e = hipMalloc((void **)&part, sizeof(double) * (size_t)std::max<int64_t>(n, 1) * cdiv(n, kRightChunk));
+    if (e != hipSuccess) goto fail;
+    h->resident = acc;
+
+    e = hipEventCreate(&e0);
+    if (e != hipSuccess) goto fail;
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) goto fail;
+    e = hipEventRecord(e0, st);
+    if (e != hipSuccess) goto fail;
+
+    e = hipMemcpy2DAsync(h->H, sizeof(double) * h->ldh, A, sizeof(double) * lda, sizeof(double) * n, n,
+                         hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) goto fail;
+    e = hipMemcpy2DAsync(h->Bw, sizeof(double) * n, B, sizeof(double) * ldb, sizeof(double) * n, m,
+                         hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) goto fail;
+    if (p > 0) {
+        e = hipMemcpy2DAsync(h->Ct, sizeof(double) * h->ldct, C, sizeof(double) * ldc, sizeof(double) * p, n,
+                             hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) goto fail;
+    }
+    e = hipMemsetAsync(h->V, 0, sizeof(double) * n * h->nrefl, st);
+    if (e != hipSuccess) goto fail;
+
+    // 1.-2. QR of B and the similarity with Q_B
+    for (int64_t j = 0; j < m; ++j) {
+        const int64_t L = n - j;
+        double *v = h->V + j * n + j;
+        double *tau = h->tauv + j;
+        hipLaunchKernelGGL(house_kernel, dim3(1), dim3(1024), 0, st, (int)L, h->Bw + j * n + j, v, tau);
+        if (m - j - 1 > 0)
+            hipLaunchKernelGGL(left_update_kernel, dim3((unsigned)(m - j - 1)), dim3(256), 0, st, (int)L, (int)j,
+                               (int)(j + 1), h->Bw, (int64_t)n, (const double *)v, (const double *)tau);
+        e = two_sided(h, h->H, h->ldh, L, j, 0, v, tau, part, st);
+        if (e != hipSuccess) goto fail;
+    }
+    // 3.-4. m-Hessenberg reduction, reflector j annihilates H(j+m+1:, j)
+    for (int64_t j = 0; j + m + 1 < n; ++j) {
+        const int64_t r0 = j + m, L = n - r0;
+        const int64_t idx = m + j;
+        double *v = h->V + idx * n + r0;
+        double *tau = h->tauv + idx;
+        hipLaunchKernelGGL(house_kernel, dim3(1), dim3(1024), 0, st, (int)L, h->H + j * h->ldh + r0, v, tau);
+        e = two_sided(h, h->H, h->ldh, L, r0, j + 1, v, tau, part, st);
+        if (e != hipSuccess) goto fail;
+    }
+    // sign normalisation and derived data
+    hipLaunchKernelGGL(signs_kernel, dim3(1), dim3(64), 0, st, (int)n, (int)m, (const double *)h->H, h->ldh,
+                       (const double *)h->Bw, (int64_t)n, h->sgn);
+    hipLaunchKernelGGL(finalize_h_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, (int)n, (int)m, h->H, h->ldh,
+                       h->H32, (const double *)h->sgn, h->offrow, h->diag);
+    hipLaunchKernelGGL(finalize_r_kernel, dim3(1), dim3(64), 0, st, (int)n, (int)m, h->Bw, (int64_t)n,
+                       (const double *)h->sgn, h->Rtop, h->rcolmax);
+    if (p > 0)
+        hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(p * n, 256)), dim3(256), 0, st, (int)p, (int)n, h->Ct,
+                           h->ldct, (const double *)h->sgn);
+    e = hipGetLastError();
+    if (e != hipSuccess) goto fail;
+    e = hipEventRecord(e1, st);
+    if (e != hipSuccess) goto fail;
+    e = hipEventSynchronize(e1);
+    if (e != hipSuccess) goto fail;
+    {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        h->reduce_ms = ms;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(part);
+    *out = h;
+    return 0;
+fail:
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(part);
+    free_handle(h);
+    return e == hipErrorOutOfMemory ? SHS_ERR_NOMEM : SHS_ERR_HIP;
+}
+
+int shs_solve_workspace(const shs_handle *h, int64_t s, int mode, int outputs, size_t *bytes)
+{
+    if (!h) return -1;
+    if (s < 0) return -2;
+    if (mode != SHS_MODE_FP64 && mode != SHS_MODE_FP32_REFINE) return -3;
+    if (!(outputs & (SHS_OUT_X | SHS_OUT_G))) return -4;
+    if (!bytes) return -5;
+    Layout L;
+    if (!layout(h, s, mode, outputs, &L)) return SHS_ERR_UNSUPPORTED;
+    *bytes = L.total;
+    return 0;
+}
+
+int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outputs, double tol, int max_iter,
+              void *work, size_t work_bytes, double *X, int64_t ldx, double *G, int64_t ldg, double *eta,
+              int32_t *status, void *stream)
+{
+    if (!h) return -1;
+    if (s < 0 || s > INT32_MAX / 64) return -2;
+    if (s > 0 && !shifts) return -3;
+    if (mode != SHS_MODE_FP64 && mode != SHS_MODE_FP32_REFINE) return -4;
+    if (!(outputs & (SHS_OUT_X | SHS_OUT_G))) return -5;
+    if (mode == SHS_MODE_FP32_REFINE && !(tol > 0.0)) return -6;
+    if (max_iter < 0) return -7;
+    if ((outputs & SHS_OUT_X) && (!X || ldx < h->n)) return -10;
+    if ((outputs & SHS_OUT_G) && h->p > 0 && (!G || ldg < h->p)) return -12;
+    if (((outputs & SHS_OUT_ETA) || mode == SHS_MODE_FP32_REFINE) && !eta) return -14;
+    if (!status) return -15;
+    if (s == 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = h->n, m = h->m;
+    Layout L;
+    if (!layout(h, s, mode, outputs, &L)) return SHS_ERR_UNSUPPORTED;
+    h->marks.clear();
+    h->refine_iterations = 0;
+    h->fallback_shifts = 0;
+    bool owned = false;
+    if (work) {
+        if (work_bytes < L.total) return -9;
+    } else {
+        RETURN_IF_HIP(hipMallocAsync(&work, L.total, st));
+        owned = true;
+    }
+    double *Xw = (outputs & SHS_OUT_X) ? X : at<double>(work, L.x);
+    const int64_t ldxw = (outputs & SHS_OUT_X) ? ldx : n;
+    int rc = 0;
+    hipError_t e = hipSuccess;
+
+    if (mode == SHS_MODE_FP64) {
+        e = solve_fp64(h, s, nullptr, shifts, work, L, Xw, ldxw, status, st);
+        if (e == hipSuccess && (outputs & SHS_OUT_ETA))
+            e = certify(h, s, nullptr, shifts, Xw, ldxw, nullptr, at<unsigned long long>(work, L.resmax),
+                        at<unsigned long long>(work, L.xmax), eta, status, s, st);
+    } else {
+        // ---- complex FP32 sweep, then FP64 iterative refinement -------------
+        Geo g32s, g32d;
+        geo(true, n, m, false, &g32s);
+        geo(true, n, m, true, &g32d);
+        int32_t *dlist = at<int32_t>(work, L.list);
+        int32_t *st2 = at<int32_t>(work, L.status2);
+        SweepArgs<float> sa{};
+        sa.n = (int)n;
+        sa.count = (int)s;
+        sa.H = h->H32;
+        sa.ldh = h->ldh;
+        sa.shifts = shifts;
+        sa.list = nullptr;
+        sa.Rtop = h->Rtop;
+        sa.refl = at<float>(work, L.refl32);
+        sa.refl_stride = g32s.stride;
+        sa.Y = at<float>(work, L.y32);
+        sa.y_stride = 2 * m * m;
+        sa.status = st2;
+        {
+            PhaseScope ps(h, PH_SWEEP32, s, st);
+            if (!launch_sweep((int)m, false, sa, st)) e = hipErrorInvalidValue;
+        }
+        QstarArgs<float> qa{};
+        qa.n = (int)n;
+        qa.count = (int)s;
+        qa.list = nullptr;
+        qa.refl = sa.refl;
+        qa.refl_stride = g32s.stride;
+        qa.tile_rows = g32s.g.tile_rows;
+        qa.tile_stride = g32s.g.tile_stride;
+        qa.slot = g32s.g.slot;
+        qa.Y = sa.Y;
+        qa.y_stride = 2 * m * m;
+        qa.X = Xw;
+        qa.ldx = ldxw;
+        qa.accumulate = 0;
+        if (e == hipSuccess) {
+            PhaseScope ps(h, PH_QSTAR, s, st);
+            if (!launch_qstar((int)m, false, qa, st)) e = hipErrorInvalidValue;
+        }
+
+        std::vector<int32_t> active(s), next, fallback;
+        for (int64_t j = 0; j < s; ++j) active[j] = (int32_t)j;
+        std::vector<double> heta(s), hprev(s, INFINITY);
+        double *Res = at<double>(work, L.res);
+        for (int it = 0; e == hipSuccess; ++it) {
+            const int64_t na = (int64_t)active.size();
+            if (na == 0) break;
+            e = hipMemcpyAsync(dlist, active.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) break;
+            e = certify(h, na, dlist, shifts, Xw, ldxw, Res, at<unsigned long long>(work, L.resmax),
+                        at<unsigned long long>(work, L.xmax), eta, nullptr, s, st);
+            if (e != hipSuccess) break;
+            e = hipMemcpyAsync(heta.data(), eta, sizeof(double) * s, hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess) break;
+            e = hipStreamSynchronize(st);
+            if (e != hipSuccess) break;
+            next.clear();
+            for (int32_t j : active) {
+                const double v = heta[j];
+                if (v <= tol) continue;                           // converged
+                if (!(v == v) || it >= max_iter || !(v <= 0.5 * hprev[j])) {
+                    fallback.push_back(j);                        // stagnated or out of iterations
+                    continue;
+                }
+                hprev[j] = v;
+                next.push_back(j);
+            }
+            active.swap(next);
+            if (active.empty()) break;
+            // correction: (H - sigma I) D = Res in FP32 (scaled), X += scale D
+            const int64_t nc = (int64_t)active.size();
+            e = hipMemcpyAsync(dlist, active.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) break;
+            h->refine_iterations++;
+            {
+                PhaseScope ps(h, PH_OTHER, nc, st);
+                hipLaunchKernelGGL(scale_residual_kernel, dim3(std::max<unsigned>(1, cdiv(n * m, 256 * 16)), (unsigned)nc),
+                                   dim3(256), 0, st, (int)n, (int)m, (int)nc, (const int32_t *)dlist,
+                                   (const double *)Res,
+                                   (const unsigned long long *)at<unsigned long long>(work, L.resmax),
+                                   at<double>(work, L.scale), at<float>(work, L.e32));
+            }
+            SweepArgs<float> da{};
+            da.n = (int)n;
+            da.count = (int)nc;
+            da.H = h->H32;
+            da.ldh = h->ldh;
+            da.shifts = shifts;
+            da.list = dlist;
+            da.Rtop = h->Rtop;
+            da.E = at<float>(work, L.e32);
+            da.e_stride = 2 * n * m;
+            da.refl = at<float>(work, L.refl32);
+            da.refl_stride = g32d.stride;
+            da.Y = at<float>(work, L.yd32);
+            da.y_stride = 2 * n * m;
+            da.status = st2;
+            {
+                PhaseScope ps(h, PH_SWEEP32D, nc, st);
+                if (!launch_sweep((int)m, true, da, st)) { e = hipErrorInvalidValue; break; }
+            }
+            QstarArgs<float> dq{};
+            dq.n = (int)n;
+            dq.count = (int)nc;
+            dq.list = dlist;
+            dq.refl = da.refl;
+            dq.refl_stride = g32d.stride;
+            dq.tile_rows = g32d.g.tile_rows;
+            dq.tile_stride = g32d.g.tile_stride;
+            dq.slot = g32d.g.slot;
+            dq.Y = da.Y;
+            dq.y_stride = 2 * n * m;
+            dq.X = Xw;
+            dq.ldx = ldxw;
+            dq.accumulate = 1;
+            dq.scale = at<double>(work, L.scale);
+            {
+                PhaseScope ps(h, PH_QSTAR, nc, st);
+                if (!launch_qstar((int)m, true, dq, st)) { e = hipErrorInvalidValue; break; }
+            }
+            e = hipGetLastError();
+        }
+        // converged shifts: status 0
+        if (e == hipSuccess) e = hipMemsetAsync(status, 0, sizeof(int32_t) * s, st);
+        if (e == hipSuccess && !fallback.empty()) {
+            // FP64 sweep for the shifts the mixed form could not certify
+            const int64_t nf = (int64_t)fallback.size();
+            h->fallback_shifts = nf;
+            e = hipMemcpyAsync(dlist, fallback.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = solve_fp64(h, nf, dlist, shifts, work, L, Xw, ldxw, st2, st);
+            if (e == hipSuccess)
+                e = certify(h, nf, dlist, shifts, Xw, ldxw, nullptr, at<unsigned long long>(work, L.resmax),
+                            at<unsigned long long>(work, L.xmax), eta, st2, s, st);
+            if (e == hipSuccess)
+                hipLaunchKernelGGL(fill_status_kernel, dim3(cdiv(nf, 256)), dim3(256), 0, st, (int)nf,
+                                   (const int32_t *)dlist, (const int32_t *)st2, status, SHS_STATUS_FALLBACK);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+        }
+    }
+    if (e == hipSuccess && (outputs & SHS_OUT_G) && h->p > 0) {
+        PhaseScope ps(h, PH_OTHER, s, st);
+        hipLaunchKernelGGL(g_eval_kernel, dim3((unsigned)(s * m)), dim3(256), 0, st, (int)n, (int)h->p, (int)m,
+                           (int)s, (const int32_t *)nullptr, (const double *)h->Ct, h->ldct, (const double *)Xw,
+                           ldxw, G, ldg);
+        e = hipGetLastError();
+    }
+    if (owned) {
+        hipError_t e2 = hipFreeAsync(work, st);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) rc = (e == hipErrorOutOfMemory) ? SHS_ERR_NOMEM : SHS_ERR_HIP;
+    return rc;
+}
+
+int shs_apply_q(const shs_handle *h, int64_t ncols, const double *Xred, int64_t ld, double *Xorig, int64_t ldo,
+                void *stream)
+{
+    if (!h) return -1;
+    if (ncols < 0) return -2;
+    if (ncols > 0 && !Xred) return -3;
+    if (ld < h->n) return -4;
+    if (ncols > 0 && !Xorig) return -5;
+    if (ldo < h->n) return -6;
+    if (ncols == 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = h->n, m = h->m;
+    if (Xorig != Xred || ld != ldo)
+        hipLaunchKernelGGL(copy_complex_kernel, dim3(cdiv(n * ncols, 256)), dim3(256), 0, st, (int)n, (int)ncols,
+                           Xred, ld, Xorig, ldo);
+    // Q = Q_B Q_A S: X <- S X, then the Q_A reflectors last to first, then Q_B's
+    hipLaunchKernelGGL(scale_rows_complex_kernel, dim3(cdiv(n * ncols, 256)), dim3(256), 0, st, (int)n,
+                       (int)ncols, Xorig, ldo, (const double *)h->sgn);
+    for (int64_t idx = h->nrefl - 1; idx >= 0; --idx) {
+        const int64_t r0 = refl_start(m, idx);
+        const int64_t L = n - r0;
+        hipLaunchKernelGGL(reflect_complex_kernel, dim3((unsigned)ncols), dim3(256), 0, st, (int)L, (int)r0, Xorig,
+                           ldo, (const double *)(h->V + idx * n + r0), (const double *)(h->tauv + idx));
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : SHS_ERR_HIP;
+}
+
+int shs_get_reduced(const shs_handle *h, double *H, int64_t ldh, double *R, int64_t ldr, double *Ct,
+                    int64_t ldct, void *stream)
+{
+    if (!h) return -1;
+    if (H && ldh < h->n) return -3;
+    if (R && ldr < h->n) return -5;
+    if (Ct && ldct < std::max<int64_t>(1, h->p)) return -7;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = h->n, m = h->m, p = h->p;
+    if (H) RETURN_IF_HIP(hipMemcpy2DAsync(H, sizeof(double) * ldh, h->H, sizeof(double) * h->ldh,
+                                          sizeof(double) * n, n, hipMemcpyDeviceToDevice, st));
+    if (R) RETURN_IF_HIP(hipMemcpy2DAsync(R, sizeof(double) * ldr, h->Bw, sizeof(double) * n, sizeof(double) * n, m,
+                                          hipMemcpyDeviceToDevice, st));
+    if (Ct && p > 0)
+        RETURN_IF_HIP(hipMemcpy2DAsync(Ct, sizeof(double) * ldct, h->Ct, sizeof(double) * h->ldct,
+                                       sizeof(double) * p, n, hipMemcpyDeviceToDevice, st));
+    return 0;
+}
+
+int shs_info(const shs_handle *h, shs_info_t *info)
+{
+    if (!h) return -1;
+    if (!info) return -2;
+    info->n = h->n;
+    info->m = h->m;
+    info->p = h->p;
+    info->reduce_ms = h->reduce_ms;
+    info->resident_bytes = h->resident;
+    return 0;
+}
+
+int shs_set_timing(shs_handle *h, int enable)
+{
+    if (!h) return -1;
+    h->timing = enable != 0;
+    h->marks.clear();
+    return 0;
+}
+
+int shs_last_timings(const shs_handle *h, shs_timings_t *out)
+{
+    if (!h) return -1;
+    if (!out) return -2;
+    std::memset(out, 0, sizeof(*out));
+    if (!h->marks.empty()) RETURN_IF_HIP(hipEventSynchronize(h->marks.back().b));
+    double *ms[PH_COUNT] = {&out->sweep_ms, &out->qstar_ms, &out->residual_ms, &out->sweep32_ms,
+                            &out->sweep32_dense_ms, &out->other_ms};
+    int64_t *calls[PH_COUNT] = {&out->sweep_calls, &out->qstar_calls, &out->residual_calls, &out->sweep32_calls,
+                                &out->sweep32_dense_calls, &out->other_calls};
+    for (const auto &mk : h->marks) {
+        float t = 0.f;
+        RETURN_IF_HIP(hipEventElapsedTime(&t, mk.a, mk.b));
+        *ms[mk.phase] += t;
+        *calls[mk.phase] += 1;
+        if (mk.phase == PH_SWEEP) out->sweep_shifts += mk.shifts;
+        if (mk.phase == PH_SWEEP32) out->sweep32_shifts += mk.shifts;
+        if (mk.phase == PH_SWEEP32D) out->sweep32_dense_shifts += mk.shifts;
+    }
+    out->refine_iterations = h->refine_iterations;
+    out->fallback_shifts = h->fallback_shifts;
+    return 0;
+}
+
+void shs_destroy(shs_handle *h)
+{
+    if (!h) return;
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipSetDevice(h->device);
+    hipDeviceSynchronize();
+    free_handle(h);
+    hipSetDevice(dev);
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// Q* pass: X = P_{n-1} ... P_1 P_0 [Y; 0] (or ... P_0 y for a dense y).
+//
+// Section 3.3 forms each solution as x = Q_sigma^*(:, 1:m) y with y the
+// small triangular solve; with Q_sigma^* = P_{n-1} ... P_0 kept as the stored
+// reflectors of the sweep, applying them to [Y; 0] from P_0 upward gives
+// exactly that product without forming Q_sigma.  Every P_k is Hermitian and
+// acts on rows k-m .. k only, so the pass walks down the rows with an
+// (m+1)-row window: step k applies P_k, then row k-m is final and leaves.
+//
+// GPU mapping: one lane per (shift, right-hand-side column); a wave holds
+// 64/m shifts.  The window again rotates through registers (logical row
+// k-m+j in slot (j + k) mod (m+1)).  Accumulation is FP64 whatever the
+// precision of the reflectors.
+#pragma once
+
+#include <utility>
+
+#include "common.hpp"
+#include "sweep.hpp"
+
+namespace shs {
+
+template <typename T>
+struct QstarArgs {
+    int n, count;
+    const int32_t *list;         // work item -> shift id (nullptr = identity)
+    const T *refl;               // reflector store of the sweep that produced Y
+    int64_t refl_stride;
+    int tile_rows;               // rows per tile of that sweep
+    int64_t tile_stride;         // elements per tile in the store
+    int slot;                    // elements per slot
+    const T *Y;                  // structured: m x m (ld m); dense: n x m (ld n)
+    int64_t y_stride;
+    double *X;                   // n x (s m) complex, ld ldx; column sid*m + c
+    int64_t ldx;
+    int accumulate;              // 0: X = D, 1: X += scale[sid] * D
+    const double *scale;         // per shift id, or nullptr (= 1)
+};
+
+template <typename T, int M, bool DENSE_IN>
+__global__ __launch_bounds__(64) void qstar_kernel(QstarArgs<T> a)
+{
+    constexpr int NP = M + 1;
+    constexpr int SPW = kWave / M;
+    const int lane = threadIdx.x;
+    const int sw = lane / M, c = lane % M;
+    const int item = blockIdx.x * SPW + sw;
+    const bool active = (sw < SPW) && (item < a.count);
+    const int sid = active ? (a.list ? a.list[item] : item) : 0;
+    const int n = a.n;
+
+    const T *rf = a.refl + (int64_t)sid * a.refl_stride;
+    const T *Y = a.Y + (int64_t)sid * a.y_stride;
+    double *X = a.X + ((int64_t)sid * M + c) * a.ldx * 2;
+    const double sc = (a.accumulate && a.scale) ? a.scale[sid] : 1.0;
+
+    auto slot_ptr = [&](int k) -> const T * {
+        const int t = k / a.tile_rows;
+        return rf + (int64_t)t * a.tile_stride + (int64_t)(k - t * a.tile_rows) * a.slot;
+    };
+    auto input_row = [&](int i, double &xr, double &xi) {
+        xr = 0.0;
+        xi = 0.0;
+        if (!active || i >= n) return;
+        if constexpr (DENSE_IN) {
+            xr = (double)Y[2 * ((int64_t)c * n + i)];
+            xi = (double)Y[2 * ((int64_t)c * n + i) + 1];
+        } else {
+            if (i < M) {
+                xr = (double)Y[2 * (c * M + i)];
+                xi = (double)Y[2 * (c * M + i) + 1];
+            }
+        }
+    };
+
+    double yr[NP], yi[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) { yr[j] = 0.0; yi[j] = 0.0; }
+    input_row(0, yr[M], yi[M]);   // phase 0: logical j in slot j; row 0 is logical m
+
+    double vr[M], vi[M], tau = 0.0;
+    double nvr[M], nvi[M], ntau = 0.0;
+    auto load = [&](int k, double (&lr)[M], double (&li)[M], double &lt) {
+        if (active && k < n) {
+            const T *p = slot_ptr(k);
+            lt = (double)p[0];
+#pragma unroll
+            for (int j = 0; j < M; ++j) { lr[j] = (double)p[2 + 2 * j]; li[j] = (double)p[3 + 2 * j]; }
+        } else {
+            lt = 0.0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) { lr[j] = 0.0; li[j] = 0.0; }
+        }
+    };
+    load(0, nvr, nvi, ntau);
+
+    const int k_last = n - 1 + M;   // steps k >= n only flush the window
+    for (int kg = 0; kg <= k_last; kg += NP) {
+        static_for<NP>([&](auto qc) {
+            constexpr int Q = decltype(qc)::value;   // k mod (m+1)
+            const int k = kg + Q;
+            if (k <= k_last) {
+#pragma unroll
+                for (int j = 0; j < M; ++j) { vr[j] = nvr[j]; vi[j] = nvi[j]; }
+                tau = ntau;
+                load(k + 1, nvr, nvi, ntau);
+                if (k < n) {
+                    // d = v^* y over rows k-m .. k (v_m = 1)
+                    constexpr int pm = (M + Q) % NP;
+                    double dr = yr[pm], di = yi[pm];
+#pragma unroll
+                    for (int j = 0; j < M; ++j) {
+                        const int p = (j + Q) % NP;
+                        // conj(v_j) * y_j
+                        dr = fma(vr[j], yr[p], fma(vi[j], yi[p], dr));
+                        di = fma(vr[j], yi[p], fma(-vi[j], yr[p], di));
+                    }
+                    const double tr = tau * dr, ti = tau * di;
+#pragma unroll
+                    for (int j = 0; j < M; ++j) {
+                        const int p = (j + Q) % NP;
+                        // y_j -= t v_j
+                        yr[p] = fma(-tr, vr[j], fma(ti, vi[j], yr[p]));
+                        yi[p] = fma(-tr, vi[j], fma(-ti, vr[j], yi[p]));
+                    }
+                    yr[pm] -= tr;
+                    yi[pm] -= ti;
+                }
+                // row k-m (logical 0, slot Q) is final
+                const int row = k - M;
+                if (active && row >= 0 && row < n) {
+                    double *px = X + 2 * (int64_t)row;
+                    if (a.accumulate) {
+                        px[0] += sc * yr[Q];
+                        px[1] += sc * yi[Q];
+                    } else {
+                        px[0] = yr[Q];
+                        px[1] = yi[Q];
+                    }
+                }
+                // row k+1 enters in the freed slot
+                input_row(k + 1, yr[Q], yi[Q]);
+            }
+        });
+    }
+}
+
+}  // namespace shs

@@ -1,0 +1,270 @@
+// FP64 residual and normwise backward error of a batch of shifted solves.
+//
+//   Res(:, j m + c) = R(:, c) - (H X_j(:, c) - sigma_j X_j(:, c))
+//   eta_j = max_c ||Res(:, jm+c)||_inf / (||H - sigma_j I||_inf ||X_j(:, c)||_inf + ||R(:, c)||_inf)
+//
+// The product H X over all shifts is one GEMM of the real n x n matrix H
+// against the stacked complex solutions (real and imaginary parts are two
+// real right-hand sides).  H is m-Hessenberg, so for a block of rows
+// [i0, i0 + 64) only columns k >= i0 - m contribute; the kernel starts its
+// k loop there and skips the zero band below.  ||H - sigma I||_inf comes
+// from the off-diagonal row sums of H computed once at reduction time, so it
+// costs O(n) per shift.
+#pragma once
+
+#include "common.hpp"
+
+namespace shs {
+
+struct ResidualArgs {
+    int n, m, count;            // count = number of listed shifts
+    const int32_t *list;        // item -> shift id (nullptr = identity)
+    const double *H;            // n x n, ld ldh
+    int64_t ldh;
+    const double *Rtop;         // m x m, ld m
+    const double *shifts;       // per shift id
+    const double *X;            // n x (s m) complex, ld ldx
+    int64_t ldx;
+    double *Res;                // optional, n x (s m) complex, ld ldr (same column layout)
+    int64_t ldr;
+    unsigned long long *resmax; // per column (s m), max |Res| (bits of a non-negative double)
+    unsigned long long *xmax;   // per column, max |X|
+};
+
+// 64 rows x 32 complex columns per workgroup of 256 threads; each thread
+// holds 4 rows x 2 columns.  Columns are indexed in the listed order:
+// work column w = item * m + c.
+__global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
+{
+    constexpr int BM = 64, BN = 32, BK = 16;
+    __shared__ double Hs[BK][BM + 1];
+    __shared__ double Xs[BK][2 * BN + 2];
+    const int tid = threadIdx.x;
+    const int tx = tid % 16, ty = tid / 16;
+    const int i0 = blockIdx.x * BM;
+    const int w0 = blockIdx.y * BN;
+    const int ncols = a.count * a.m;
+    const int n = a.n, m = a.m;
+
+    // column pointers of this thread's 2 work columns (for loads of X tiles
+    // each thread loads by (kk, cc) instead)
+    double acc_r[4][2], acc_i[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) { acc_r[r][q] = 0.0; acc_i[r][q] = 0.0; }
+
+    int kstart = i0 - m;
+    if (kstart < 0) kstart = 0;
+    kstart = (kstart / BK) * BK;
+    for (int k0 = kstart; k0 < n; k0 += BK) {
+        // H tile: rows i0..i0+63, cols k0..k0+15 ; 1024 values, 4 per thread
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = tid + e * 256;
+            const int rr = idx % BM, kk = idx / BM;
+            const int i = i0 + rr, k = k0 + kk;
+            Hs[kk][rr] = (i < n && k < n) ? a.H[(int64_t)k * a.ldh + i] : 0.0;
+        }
+        // X tile: rows k0..k0+15, 32 complex work columns; 512 complex, 2 per thread
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int idx = tid + e * 256;
+            const int kk = idx % BK, cc = idx / BK;
+            const int k = k0 + kk, wc = w0 + cc;
+            double xr = 0.0, xi = 0.0;
+            if (k < n && wc < ncols) {
+                const int item = wc / m, c = wc % m;
+                const int sid = a.list ? a.list[item] : item;
+                const double *px = a.X + (((int64_t)sid * m + c) * a.ldx + k) * 2;
+                xr = px[0];
+                xi = px[1];
+            }
+            Xs[kk][2 * cc] = xr;
+            Xs[kk][2 * cc + 1] = xi;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; ++kk) {
+            double hv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) hv[r] = Hs[kk][ty * 4 + r];
+            double xr[2], xi[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) { xr[q] = Xs[kk][2 * (tx * 2 + q)]; xi[q] = Xs[kk][2 * (tx * 2 + q) + 1]; }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    acc_r[r][q] = fma(hv[r], xr[q], acc_r[r][q]);
+                    acc_i[r][q] = fma(hv[r], xi[q], acc_i[r][q]);
+                }
+        }
+        __syncthreads();
+    }
+
+    // epilogue: Res = R - HX + sigma X, column maxima
+    __shared__ double colmax_r[16][BN];
+    __shared__ double colmax_x[16][BN];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int cc = tx * 2 + q;
+        const int wc = w0 + cc;
+        double mr = 0.0, mx = 0.0;
+        if (wc < ncols) {
+            const int item = wc / m, c = wc % m;
+            const int sid = a.list ? a.list[item] : item;
+            const double sr = a.shifts[2 * sid], si = a.shifts[2 * sid + 1];
+            const int64_t col = (int64_t)sid * m + c;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + ty * 4 + r;
+                if (i < n) {
+                    const double *px = a.X + (col * a.ldx + i) * 2;
+                    const double xr = px[0], xi = px[1];
+                    double rr = (i < m) ? a.Rtop[c * m + i] : 0.0;
+                    double ri = 0.0;
+                    rr = rr - acc_r[r][q] + (sr * xr - si * xi);
+                    ri = ri - acc_i[r][q] + (sr * xi + si * xr);
+                    if (a.Res) {
+                        double *pr = a.Res + (col * a.ldr + i) * 2;
+                        pr[0] = rr;
+                        pr[1] = ri;
+                    }
+                    const double ar = hypot(rr, ri), ax = hypot(xr, xi);
+                    // NaN must propagate into the maximum
+                    mr = (ar > mr || ar != ar) ? ar : mr;
+                    mx = (ax > mx || ax != ax) ? ax : mx;
+                }
+            }
+        }
+        colmax_r[ty][cc] = mr;
+        colmax_x[ty][cc] = mx;
+    }
+    __syncthreads();
+    if (tid < BN) {
+        const int wc = w0 + tid;
+        if (wc < ncols) {
+            double mr = 0.0, mx = 0.0;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const double vr = colmax_r[t][tid], vx = colmax_x[t][tid];
+                mr = (vr > mr || vr != vr) ? vr : mr;
+                mx = (vx > mx || vx != vx) ? vx : mx;
+            }
+            const int item = wc / m, c = wc % m;
+            const int sid = a.list ? a.list[item] : item;
+            const int64_t col = (int64_t)sid * m + c;
+            // a NaN has the largest unsigned pattern of all doubles with the sign bit clear
+            if (mr != mr) mr = __longlong_as_double(0x7ff8000000000000LL);
+            if (mx != mx) mx = __longlong_as_double(0x7ff8000000000000LL);
+            atomic_max_nonneg(a.resmax + col, mr);
+            atomic_max_nonneg(a.xmax + col, mx);
+        }
+    }
+}
+
+// eta per listed shift; updates status (NaN -> NONFINITE).
+__global__ __launch_bounds__(256) void eta_kernel(int n, int m, int count, const int32_t *list,
+                                                  const double *shifts, const double *offrow,
+                                                  const double *diag, const double *rcolmax,
+                                                  const unsigned long long *resmax,
+                                                  const unsigned long long *xmax,
+                                                  double *eta, int32_t *status)
+{
+    const int item = blockIdx.x;
+    if (item >= count) return;
+    const int sid = list ? list[item] : item;
+    const double sr = shifts[2 * sid], si = shifts[2 * sid + 1];
+    double nh = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double v = offrow[i] + hypot(diag[i] - sr, si);
+        nh = v > nh ? v : nh;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(nh, off);
+        nh = o > nh ? o : nh;
+    }
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = nh;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        nh = red[0];
+        for (int w = 1; w < 4; ++w) nh = red[w] > nh ? red[w] : nh;
+        double e = 0.0;
+        bool bad = false;
+        for (int c = 0; c < m; ++c) {
+            const int64_t col = (int64_t)sid * m + c;
+            const double rmx = __longlong_as_double((long long)resmax[col]);
+            const double xmx = __longlong_as_double((long long)xmax[col]);
+            const double den = nh * xmx + rcolmax[c];
+            double v;
+            if (rmx != rmx || xmx != xmx) { v = rmx + xmx; bad = true; }
+            else v = den > 0.0 ? rmx / den : (rmx > 0.0 ? __longlong_as_double(0x7ff0000000000000LL) : 0.0);
+            e = (v > e || v != v) ? v : e;
+        }
+        eta[sid] = e;
+        if (bad && status && status[sid] == 0) status[sid] = 2;
+    }
+}
+
+// G(:, col) = Ct X(:, col) for the columns of the listed shifts.
+// One workgroup per column; rows of Ct are taken 8 at a time.
+__global__ __launch_bounds__(256) void g_eval_kernel(int n, int p, int m, int count, const int32_t *list,
+                                                     const double *Ct, int64_t ldct,
+                                                     const double *X, int64_t ldx,
+                                                     double *G, int64_t ldg)
+{
+    constexpr int PC = 8;
+    const int wi = blockIdx.x;            // work column = item * m + c
+    const int item = wi / m, c = wi % m;
+    if (item >= count) return;
+    const int sid = list ? list[item] : item;
+    const int64_t col = (int64_t)sid * m + c;
+    const double *x = X + col * ldx * 2;
+    __shared__ double red[PC * 2][256 / kWave];
+    const int tid = threadIdx.x;
+    for (int r0 = 0; r0 < p; r0 += PC) {
+        double ar[PC], ai[PC];
+#pragma unroll
+        for (int q = 0; q < PC; ++q) { ar[q] = 0.0; ai[q] = 0.0; }
+        for (int i = tid; i < n; i += 256) {
+            const double xr = x[2 * (int64_t)i], xi = x[2 * (int64_t)i + 1];
+            const double *cc = Ct + (int64_t)i * ldct + r0;
+#pragma unroll
+            for (int q = 0; q < PC; ++q) {
+                if (r0 + q < p) {
+                    const double cv = cc[q];
+                    ar[q] = fma(cv, xr, ar[q]);
+                    ai[q] = fma(cv, xi, ai[q]);
+                }
+            }
+        }
+        // wave reduction then across the 4 waves
+#pragma unroll
+        for (int q = 0; q < PC; ++q) {
+            for (int off = 32; off > 0; off >>= 1) {
+                ar[q] += __shfl_xor(ar[q], off);
+                ai[q] += __shfl_xor(ai[q], off);
+            }
+        }
+        const int wv = tid / kWave;
+        if ((tid & 63) == 0) {
+#pragma unroll
+            for (int q = 0; q < PC; ++q) { red[2 * q][wv] = ar[q]; red[2 * q + 1][wv] = ai[q]; }
+        }
+        __syncthreads();
+        if (tid < 2 * PC) {
+            const int q = tid / 2;
+            if (r0 + q < p) {
+                double sacc = 0.0;
+#pragma unroll
+                for (int w = 0; w < 256 / kWave; ++w) sacc += red[tid][w];
+                G[2 * (col * ldg + r0 + q) + (tid & 1)] = sacc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace shs

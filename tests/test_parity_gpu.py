@@ -1,0 +1,209 @@
+"""GPU path vs the oracle, element by element, through the C ABI.
+
+Tolerances (spec acceptance): relative forward error <= 1e-10 per
+shift (checked element-wise against the shift's Frobenius norm) on shifts at
+least 1e-2 ||A||_2 away from the spectrum, and normwise backward error
+eta <= 1e-13 on every shift, computed twice: by the library's FP64 residual
+kernel and independently in NumPy.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FWD_TOL = 1e-10
+ETA_TOL = 1e-13
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1708_06290_amd  # noqa: F401  (raises if the library is not built)
+
+
+def _blocks(X, m):
+    s = X.shape[1] // m
+    return [X[:, j * m:(j + 1) * m] for j in range(s)]
+
+
+def _check_against(Xg, Xo, m, mask=None, tol=FWD_TOL, what="X"):
+    for j, (xg, xo) in enumerate(zip(_blocks(Xg, m), _blocks(Xo, m))):
+        if mask is not None and not mask[j]:
+            continue
+        scale = np.linalg.norm(xo)
+        err = np.abs(xg - xo).max()
+        assert err <= tol * scale, f"{what} shift {j}: max|diff| {err:.3e} > {tol:g} * {scale:.3e}"
+
+
+def _run(n, m, p, shifts, seed, mode=None):
+    import paper_1708_06290_amd as ss
+    A, B, C = workloads.system(n, m, p, seed)
+    sysm = ss.System(A, B, C)
+    kw = {} if mode is None else {"mode": mode}
+    res = sysm.solve(shifts, **kw)
+    torch.cuda.synchronize()
+    return A, B, C, sysm, res
+
+
+CASES = [
+    # (n, m, p, s, seed)  -- several row tiles and ragged tails for every m
+    (512, 1, 1, 64, workloads.C1.seed),   # the CPU-sized workload, all shifts
+    (700, 8, 8, 5, 11),
+    (300, 4, 2, 6, 12),
+    (257, 3, 2, 4, 13),
+    (1100, 2, 3, 3, 14),
+    (129, 16, 3, 3, 15),
+    (400, 5, 1, 3, 16),
+    (333, 7, 4, 3, 17),
+    (530, 11, 2, 2, 18),
+]
+
+
+@pytest.mark.parametrize("n,m,p,s,seed", CASES)
+def test_fp64_solve_matches_oracle(n, m, p, s, seed):
+    _need_gpu()
+    shifts = workloads.C1.shifts() if n == 512 and s == 64 else workloads.imag_axis_shifts(1e-2, 1e2, s)
+    print(f"case n={n} m={m} p={p} s={s} seed={seed}", flush=True)
+    A, B, C, sysm, res = _run(n, m, p, shifts, seed)
+    status = res.status.cpu().numpy()
+    assert (status == 0).all(), status
+    H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
+    X = res.X.cpu().numpy()
+    G = res.G.cpu().numpy()
+    eta = res.eta.cpu().numpy()
+    # spectral-distance filter for the forward-error check
+    dist = oracle.spectral_distance(A, shifts)
+    keep = dist >= 1e-2 * np.linalg.norm(A, 2)
+    assert keep.all()
+    # 1. reduced coordinates: the sweep alone against the oracle on (H, R, Ct)
+    Xo, Go, eta_o, st_o = oracle.solve(H, R, Ct, shifts)
+    _check_against(X, Xo, m, keep, what="X (reduced)")
+    _check_against(G, Go, m, keep, what="G")
+    # 2. backward error, from the library and independently from NumPy
+    assert (eta <= ETA_TOL).all(), eta.max()
+    for j, sg in enumerate(shifts):
+        assert oracle.backward_error(H, R, X[:, j * m:(j + 1) * m], sg) <= ETA_TOL
+    # 3. end to end: Q X against the oracle on the original (A, B, C)
+    Xa = sysm.apply_q(res.X).cpu().numpy()
+    Xoa, Goa, _, _ = oracle.solve(A, B, C, shifts)
+    _check_against(Xa, Xoa, m, keep, what="Q X")
+    _check_against(G, Goa, m, keep, what="G vs original")
+
+
+def test_fp64_degenerate_shapes():
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    for (n, m, p) in [(2, 1, 1), (5, 4, 2), (17, 16, 3), (65, 1, 1), (64, 8, 2), (63, 2, 0)]:
+        print(f"shape n={n} m={m} p={p}", flush=True)
+        A, B, C = workloads.system(n, m, p, 100 + n)
+        shifts = workloads.imag_axis_shifts(1e-1, 1e1, 3)
+        sysm = ss.System(A, B, C)
+        res = sysm.solve(shifts)
+        assert (res.status.cpu().numpy() == 0).all()
+        H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
+        Xo, Go, _, _ = oracle.solve(H, R, Ct if p > 0 else np.zeros((0, n)), shifts)
+        _check_against(res.X.cpu().numpy(), Xo, m)
+        if p > 0:
+            _check_against(res.G.cpu().numpy(), Go, m, what="G")
+        assert (res.eta.cpu().numpy() <= ETA_TOL).all()
+
+
+def test_already_reduced_input_and_singular_shift():
+    """Upper-triangular A is already m-Hessenberg; sigma = A(k,k) is exactly singular."""
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    n, m = 150, 3
+    rng = np.random.default_rng(7)
+    A = np.triu(rng.standard_normal((n, n)))
+    np.fill_diagonal(A, np.linspace(-2.0, -0.5, n))
+    B = np.zeros((n, m))
+    B[:m, :] = np.triu(rng.standard_normal((m, m))) + 2 * np.eye(m)
+    C = rng.standard_normal((2, n))
+    kk = 77
+    shifts = np.array([0.5j, A[kk, kk] + 0j, -1.0 + 0.25j, 1e6j])
+    sysm = ss.System(A, B, C)
+    res = sysm.solve(shifts)
+    st = res.status.cpu().numpy()
+    assert list(st) == [0, ss.SHS_STATUS_SINGULAR, 0, 0], st
+    X = res.X.cpu().numpy()
+    assert np.isnan(X[:, m:2 * m]).all()
+    H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
+    good = np.array([0, 2, 3])
+    Xo, Go, _, _ = oracle.solve(H, R, Ct, shifts[good])
+    for q, j in enumerate(good):
+        xo = Xo[:, q * m:(q + 1) * m]
+        assert np.abs(X[:, j * m:(j + 1) * m] - xo).max() <= FWD_TOL * np.linalg.norm(xo)
+
+
+def test_nonfinite_input_is_flagged():
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    A, B, C = workloads.system(100, 2, 1, 3)
+    A[10, 20] = np.nan
+    sysm = ss.System(A, B, C)
+    res = sysm.solve(np.array([1j, 2j]))
+    st = res.status.cpu().numpy()
+    assert (st == ss.SHS_STATUS_NONFINITE).all(), st
+
+
+def test_reduction_invariants_and_oracle():
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    n, m, p = 300, 4, 3
+    A, B, C = workloads.system(n, m, p, 21)
+    sysm = ss.System(A, B, C)
+    H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
+    eye = torch.eye(n, dtype=torch.complex128, device="cuda")
+    Q = sysm.apply_q(eye).cpu().numpy().real
+    u = np.finfo(float).eps
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 50 * n * u
+    assert np.linalg.norm(Q.T @ A @ Q - H) <= 50 * n * u * np.linalg.norm(A)
+    assert np.linalg.norm(Q.T @ B - R) <= 50 * n * u * np.linalg.norm(B)
+    assert np.linalg.norm(C @ Q - Ct) <= 50 * n * u * np.linalg.norm(C)
+    i, j = np.indices((n, n))
+    assert (H[i > j + m] == 0).all()
+    assert (R[m:] == 0).all() and (np.tril(R[:m], -1) == 0).all()
+    assert (np.diag(R[:m]) >= 0).all() and all(H[k + m, k] >= 0 for k in range(n - m))
+    Ho, Ro, Cto, Qo = oracle.reduce(A, B, C)
+    assert np.abs(H - Ho).max() <= 1e-9 * np.abs(A).max()
+    assert np.abs(R - Ro).max() <= 1e-9 * np.abs(B).max()
+    assert np.abs(Ct - Cto).max() <= 1e-9 * np.abs(C).max()
+
+
+def test_fp32_refine_matches_oracle():
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    n, m, p, s = 600, 4, 2, 12
+    shifts = workloads.imag_axis_shifts(1e-3, 1e3, s)
+    A, B, C, sysm, res = _run(n, m, p, shifts, 31, mode=ss.SHS_MODE_FP32_REFINE)
+    st = res.status.cpu().numpy()
+    assert np.isin(st, [0, ss.SHS_STATUS_FALLBACK]).all(), st
+    eta = res.eta.cpu().numpy()
+    assert (eta <= ETA_TOL).all(), eta
+    H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
+    X = res.X.cpu().numpy()
+    Xo, Go, _, _ = oracle.solve(H, R, Ct, shifts)
+    _check_against(X, Xo, m)
+    _check_against(res.G.cpu().numpy(), Go, m, what="G")
+    for j, sg in enumerate(shifts):
+        assert oracle.backward_error(H, R, X[:, j * m:(j + 1) * m], sg) <= ETA_TOL
+
+
+def test_batch_invariance_and_determinism():
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    A, B, C = workloads.system(400, 4, 2, 41)
+    shifts = workloads.imag_axis_shifts(1e-2, 1e2, 9)
+    sysm = ss.System(A, B, C)
+    r1 = sysm.solve(shifts)
+    r2 = sysm.solve(shifts)
+    r3 = sysm.solve(shifts[3:5])
+    X1, X2, X3 = (r.X.cpu().numpy() for r in (r1, r2, r3))
+    assert np.array_equal(X1, X2)
+    assert np.array_equal(X1[:, 12:20], X3)

@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle shifts (0 = automatic)")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink n and s (smoke runs only)")
+    ap.add_argument("--serve-requests", type=int, default=150,
+                    help="requests per load level in the serving leg (0 = skip the leg)")
+    ap.add_argument("--serve-scale", type=float, default=1.0, help="scale n of the serving systems")
+    ap.add_argument("--serve-only", action="store_true")
     return ap.parse_args()
 
 
@@ -76,6 +80,9 @@ def main():
 
     import paper_1708_06290_amd as ss
 
+    if args.serve_only:
+        print(json.dumps({"serving": serving_leg(args)}))
+        return
     wl = {"c1": workloads.C1, "c2": workloads.C2, "c3": workloads.C3, "c5": workloads.C5}[args.workload]
     n = max(wl.m + 1, int(wl.n * args.scale))
     s = max(1, int(wl.s * args.scale))
@@ -160,6 +167,10 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(sysm, shifts, args.cpu_sample, n, m)
+    del Xs, Gs
+    sysm.close()
+    torch.cuda.empty_cache()
+    serving = serving_leg(args) if args.serve_requests > 0 else None
 
     head = results.get("fp64") or results.get("mixed")
     line = {
@@ -182,8 +193,88 @@ def main():
         "cpu_baseline": cpu,
         "fp64": results.get("fp64"),
         "mixed": results.get("mixed"),
+        "serving": serving,
     }
     print(json.dumps(line))
+
+
+def serving_leg(args):
+    """Continuous-batching server over the eight resident systems of the
+    serving mix (n in {1024..8192}, m in {1,2,4,16}, p = m): capacity from a
+    closed burst, then Poisson arrivals at 50% and 80% of it; requests hold
+    16..512 imaginary shifts, FP64 and mixed-precision interleaved."""
+    import torch
+
+    import paper_1708_06290_amd as ss
+    t0 = time.time()
+    systems = []
+    for i in range(len(workloads.SERVE_SYSTEMS)):
+        A, B, C = workloads.serve_system(i, args.serve_scale)
+        systems.append(ss.System(A, B, C))
+    red_ms = [round(sy.info()["reduce_ms"], 1) for sy in systems]
+    print(f"# serving: {len(systems)} systems reduced in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    def run(reqs, rate_hz, label):
+        srv = ss.Server(streams=4, budget_bytes=64 << 30, max_batch=64)
+        ids = [srv.register(sy) for sy in systems]
+        handles = []
+        t_start = time.perf_counter()
+        for (t_arr, sys_id, shifts, mode) in reqs:
+            if rate_hz is not None:
+                delay = t_arr - (time.perf_counter() - t_start)
+                if delay > 0:
+                    time.sleep(delay)
+            md = ss.SHS_MODE_FP64 if mode == "fp64" else ss.SHS_MODE_FP32_REFINE
+            handles.append((srv.submit(ids[sys_id], shifts, mode=md), sys_id, shifts, mode))
+        for (h, _, _, _) in handles:
+            srv.wait(h, timeout_ms=600000)
+        el = time.perf_counter() - t_start
+        st = srv.stats()
+        bad = 0
+        for (h, _, _, _) in handles:
+            e = h.eta.cpu().numpy() if h.eta is not None else None
+            if e is not None and not (e <= 1e-13).all():
+                bad += 1
+        out = {"requests": len(reqs), "rate_hz": rate_hz, "wall_s": round(el, 3),
+               "solves_per_s": round(st["solves"] / el, 2), "p50_ms": round(st["p50_ms"], 2),
+               "p99_ms": round(st["p99_ms"], 2), "max_ms": round(st["max_ms"], 2),
+               "batches": st["batches"], "max_batch_systems": st["max_batch_systems"],
+               "failed": st["failed"], "uncertified": bad}
+        print(f"# serving {label}: {out}", file=sys.stderr, flush=True)
+        return out, handles, srv
+
+    nreq = args.serve_requests
+    burst = workloads.request_stream(min(nreq, 64), rate_hz=1e9, seed=workloads.ARRIVAL_SEED + 1)
+    cal, _, srv = run(burst, None, "burst")
+    srv.close()
+    cap = cal["requests"] / cal["wall_s"]
+    levels = {}
+    keep = None
+    for frac in (0.5, 0.8):
+        reqs = workloads.request_stream(nreq, rate_hz=frac * cap, seed=workloads.ARRIVAL_SEED)
+        res, handles, srv = run(reqs, frac * cap, f"{int(frac * 100)}%")
+        levels[f"load_{int(frac * 100)}"] = res
+        if keep is None:
+            keep = (handles[:6], srv)
+        else:
+            srv.close()
+    # the same requests alone: FP64 results must be bitwise equal to the mix
+    handles, srv = keep
+    same = 0
+    checked = 0
+    for (h, sys_id, shifts, mode) in handles:
+        if mode != "fp64":
+            continue
+        alone = systems[sys_id].solve(shifts)
+        torch.cuda.synchronize()
+        checked += 1
+        same += int(torch.equal(alone.X, h.X.t()))
+    srv.close()
+    for sy in systems:
+        sy.close()
+    return {"systems": [list(x) for x in workloads.SERVE_SYSTEMS], "n_scale": args.serve_scale,
+            "reduce_ms": red_ms, "capacity_req_per_s": round(cap, 2), "burst": cal, **levels,
+            "alone_vs_mix_bitwise": f"{same}/{checked}"}
 
 
 def cpu_baseline(sysm, shifts, sample, n, m):

@@ -206,6 +206,78 @@ typedef struct shs_timings_t {
 int shs_set_timing(shs_handle *h, int enable);
 int shs_last_timings(const shs_handle *h, shs_timings_t *out);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: resident systems, continuous batching of shift requests.         */
+/* ------------------------------------------------------------------------ */
+/*
+ * A server keeps reduced systems (handles) resident on the current GPU and
+ * runs shift requests from many clients.  Worker threads, one per HIP stream,
+ * take work as soon as they are free: FP64 requests that are waiting are
+ * batched into one launch of the work-item kernel (shifts of different
+ * systems, with different n and m, in the same launch), a mixed-precision
+ * request runs as one shs_solve on its worker's stream.  A request is
+ * admitted only when its workspace (shs_solve_workspace bytes) fits in what
+ * is left of the device-memory budget; requests that arrive while others
+ * run are admitted as workers and memory free up, so their work overlaps on
+ * the device.  Latency is stamped at submit and at completion.
+ *
+ * Thread-safe: any thread may submit, poll and wait.  The server never owns
+ * the handles it serves; destroy the server before them.  Do not enable
+ * phase timing (shs_set_timing) on a handle a server uses.
+ */
+typedef struct shs_server shs_server;
+
+typedef struct shs_server_config {
+    int32_t abi_version;    /* must be SHS_ABI_VERSION */
+    int32_t streams;        /* worker threads / HIP streams (>= 1) */
+    int64_t budget_bytes;   /* device-memory budget for request workspaces */
+    int32_t max_batch;      /* most requests per FP64 batch (>= 1) */
+    int32_t flags;          /* reserved, 0 */
+    int64_t reserved[4];
+} shs_server_config;
+
+typedef struct shs_server_stats_t {
+    int64_t submitted, completed, failed, queued, running;
+    int64_t solves;              /* shifts completed */
+    int64_t batches;             /* FP64 work-item launches */
+    int64_t max_batch_systems;   /* most distinct systems in one launch */
+    double  p50_ms, p99_ms, max_ms, mean_ms;   /* submit -> completion */
+    double  busy_s;              /* wall time from first submit to last completion */
+    int64_t peak_bytes;          /* largest admitted workspace total */
+} shs_server_stats_t;
+
+int shs_server_create(const shs_server_config *cfg, shs_server **out);
+
+/* Make a handle servable; *sys_id receives its id.  The handle must belong
+ * to the server's device. */
+int shs_server_register(shs_server *srv, shs_handle *h, int32_t *sys_id);
+
+/*
+ * Queue a request: s shifts (host array, copied before return) on system
+ * sys_id with mode/outputs as for shs_solve.  X, G, eta, status are device
+ * arrays laid out as in shs_solve; they must stay valid until the request
+ * completes.  *req_id receives the request id.  Returns SHS_ERR_NOMEM if the
+ * request alone exceeds the budget, SHS_ERR_NOTFOUND for an unknown system.
+ */
+int shs_server_submit(shs_server *srv, int32_t sys_id, int64_t s, const double *shifts_host,
+                      int mode, int outputs, double *X, int64_t ldx, double *G, int64_t ldg,
+                      double *eta, int32_t *status, int64_t *req_id);
+
+/* *state: 0 queued, 1 running, 2 done, 3 failed. */
+int shs_server_poll(shs_server *srv, int64_t req_id, int *state);
+
+/* Wait until the request completes (timeout_ms < 0: no limit).  Returns 0,
+ * SHS_ERR_TIMEOUT, or the error the request failed with. */
+int shs_server_wait(shs_server *srv, int64_t req_id, double timeout_ms);
+
+/* Submit -> completion latency of a completed request, milliseconds. */
+int shs_server_latency(shs_server *srv, int64_t req_id, double *ms);
+
+int shs_server_stats(shs_server *srv, shs_server_stats_t *out);
+
+/* Waits for all requests, stops the workers and frees the server. */
+void shs_server_destroy(shs_server *srv);
+
 /* Release a handle and all device memory it owns (synchronises its device). */
 void shs_destroy(shs_handle *h);
 

@@ -17,11 +17,15 @@ import dataclasses
 from ._lib import (SHS_MAX_M, SHS_MODE_FP32_REFINE, SHS_MODE_FP64, SHS_OUT_ETA, SHS_OUT_G, SHS_OUT_X,
                    SHS_STATUS_FALLBACK, SHS_STATUS_NONFINITE, SHS_STATUS_NOT_CONVERGED, SHS_STATUS_OK,
                    SHS_STATUS_SINGULAR, ShsError, library, shs_apply_q, shs_destroy, shs_get_reduced,
-                   shs_info, shs_last_timings, shs_reduce, shs_set_timing, shs_solve, shs_solve_workspace)
+                   shs_info, shs_last_timings, shs_reduce, shs_server_create, shs_server_destroy,
+                   shs_server_latency, shs_server_poll, shs_server_register, shs_server_stats, shs_server_submit,
+                   shs_server_wait, shs_set_timing, shs_solve, shs_solve_workspace)
 
 __all__ = ["System", "SolveResult", "library", "shs_reduce", "shs_solve", "shs_solve_workspace",
            "shs_apply_q", "shs_get_reduced", "shs_info", "shs_set_timing", "shs_last_timings",
-           "shs_destroy", "ShsError",
+           "shs_destroy", "ShsError", "Server", "Request", "shs_server_create", "shs_server_register",
+           "shs_server_submit", "shs_server_poll", "shs_server_wait", "shs_server_latency", "shs_server_stats",
+           "shs_server_destroy",
            "SHS_MODE_FP64", "SHS_MODE_FP32_REFINE", "SHS_OUT_X", "SHS_OUT_G", "SHS_OUT_ETA",
            "SHS_STATUS_OK", "SHS_STATUS_SINGULAR", "SHS_STATUS_NONFINITE", "SHS_STATUS_FALLBACK",
            "SHS_STATUS_NOT_CONVERGED", "SHS_MAX_M"]
@@ -114,3 +118,73 @@ class System:
         out = torch.empty_like(Xs)
         shs_apply_q(self.handle, Xs, out, stream)
         return out.t()
+
+
+@dataclasses.dataclass
+class Request:
+    id: int
+    system: "System"
+    X: object
+    G: object
+    eta: object
+    status: object
+
+    def result(self):
+        s = self.status.numel()
+        m, p = self.system.m, self.system.p
+        X = self.X.t() if self.X is not None else None
+        G = self.G.t()[:p] if self.G is not None else None
+        return SolveResult(X, G, self.eta, self.status)
+
+
+class Server:
+    """Continuous-batching server over resident systems (see shs_server_* in shiftsolve.h)."""
+
+    def __init__(self, streams=4, budget_bytes=64 << 30, max_batch=64):
+        self.handle = shs_server_create(streams, budget_bytes, max_batch)
+        self.systems = []
+
+    def register(self, system: "System") -> int:
+        sid = shs_server_register(self.handle, system.handle)
+        self.systems.append(system)
+        return sid
+
+    def submit(self, sys_id, shifts, mode=SHS_MODE_FP64, outputs=SHS_OUT_X | SHS_OUT_G | SHS_OUT_ETA) -> Request:
+        import numpy as np
+        import torch
+        sysm = self.systems[sys_id]
+        shifts = np.asarray(shifts, dtype=np.complex128).reshape(-1)
+        s, n, m, p = shifts.size, sysm.n, sysm.m, sysm.p
+        X = torch.empty((s * m, n), dtype=torch.complex128, device=sysm.device) if outputs & SHS_OUT_X else None
+        G = (torch.empty((s * m, max(1, p)), dtype=torch.complex128, device=sysm.device)
+             if (outputs & SHS_OUT_G) and p > 0 else None)
+        eta = (torch.empty(s, dtype=torch.float64, device=sysm.device)
+               if (outputs & SHS_OUT_ETA) or mode == SHS_MODE_FP32_REFINE else None)
+        status = torch.empty(s, dtype=torch.int32, device=sysm.device)
+        torch.cuda.synchronize()   # the server's streams must see the allocations
+        rid = shs_server_submit(self.handle, sys_id, shifts, X, G, eta, status, mode=mode, outputs=outputs)
+        return Request(rid, sysm, X, G, eta, status)
+
+    def wait(self, req: Request, timeout_ms=-1.0):
+        shs_server_wait(self.handle, req.id, timeout_ms)
+        return req.result()
+
+    def poll(self, req: Request) -> int:
+        return shs_server_poll(self.handle, req.id)
+
+    def latency_ms(self, req: Request) -> float:
+        return shs_server_latency(self.handle, req.id)
+
+    def stats(self):
+        return shs_server_stats(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            shs_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

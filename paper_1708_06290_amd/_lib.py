@@ -28,7 +28,9 @@ SHS_MAX_M = 16
 
 EXPORTED = ("shs_reduce", "shs_solve_workspace", "shs_solve", "shs_apply_q", "shs_get_reduced",
             "shs_info", "shs_set_timing", "shs_last_timings", "shs_destroy", "shs_strerror",
-            "shs_abi_version")
+            "shs_abi_version", "shs_server_create", "shs_server_register", "shs_server_submit",
+            "shs_server_poll", "shs_server_wait", "shs_server_latency", "shs_server_stats",
+            "shs_server_destroy")
 
 _lib = None
 
@@ -52,6 +54,18 @@ class _Timings(ctypes.Structure):
                                               "sweep32_dense_calls", "other_calls", "sweep_shifts",
                                               "sweep32_shifts", "sweep32_dense_shifts", "refine_iterations",
                                               "fallback_shifts")]
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("streams", ctypes.c_int32), ("budget_bytes", ctypes.c_int64),
+                ("max_batch", ctypes.c_int32), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int64 * 4)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("submitted", "completed", "failed", "queued", "running", "solves",
+                                              "batches", "max_batch_systems")] + \
+               [(f, ctypes.c_double) for f in ("p50_ms", "p99_ms", "max_ms", "mean_ms", "busy_s")] + \
+               [("peak_bytes", ctypes.c_int64)]
 
 
 class _Config(ctypes.Structure):
@@ -85,6 +99,23 @@ def _load():
     lib.shs_set_timing.restype = ctypes.c_int
     lib.shs_last_timings.argtypes = [vp, ctypes.POINTER(_Timings)]
     lib.shs_last_timings.restype = ctypes.c_int
+    lib.shs_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
+    lib.shs_server_create.restype = ctypes.c_int
+    lib.shs_server_register.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.shs_server_register.restype = ctypes.c_int
+    lib.shs_server_submit.argtypes = [vp, ctypes.c_int32, i64, dp, ctypes.c_int, ctypes.c_int, dp, i64, dp, i64,
+                                      dp, vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.shs_server_submit.restype = ctypes.c_int
+    lib.shs_server_poll.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_int)]
+    lib.shs_server_poll.restype = ctypes.c_int
+    lib.shs_server_wait.argtypes = [vp, i64, ctypes.c_double]
+    lib.shs_server_wait.restype = ctypes.c_int
+    lib.shs_server_latency.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
+    lib.shs_server_latency.restype = ctypes.c_int
+    lib.shs_server_stats.argtypes = [vp, ctypes.POINTER(_ServerStats)]
+    lib.shs_server_stats.restype = ctypes.c_int
+    lib.shs_server_destroy.argtypes = [vp]
+    lib.shs_server_destroy.restype = None
     lib.shs_destroy.argtypes = [vp]
     lib.shs_destroy.restype = None
     lib.shs_strerror.argtypes = [ctypes.c_int]
@@ -213,3 +244,62 @@ def shs_last_timings(h):
 
 def shs_destroy(h):
     _load().shs_destroy(h)
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+def shs_server_create(streams=4, budget_bytes=64 << 30, max_batch=64):
+    lib = _load()
+    cfg = _ServerConfig(abi_version=SHS_ABI_VERSION, streams=streams, budget_bytes=budget_bytes,
+                        max_batch=max_batch)
+    srv = ctypes.c_void_p()
+    _check("shs_server_create", lib.shs_server_create(ctypes.byref(cfg), ctypes.byref(srv)))
+    return srv
+
+
+def shs_server_register(srv, h):
+    sid = ctypes.c_int32()
+    _check("shs_server_register", _load().shs_server_register(srv, h, ctypes.byref(sid)))
+    return sid.value
+
+
+def shs_server_submit(srv, sys_id, shifts_host, X, G, eta, status, mode=SHS_MODE_FP64,
+                      outputs=SHS_OUT_X | SHS_OUT_G):
+    """Queue a request; shifts_host is a 1-D complex128 NumPy array (copied)."""
+    import numpy as np
+    sh = np.ascontiguousarray(np.asarray(shifts_host, dtype=np.complex128).reshape(-1))
+    rid = ctypes.c_int64()
+    ldx = X.shape[1] if X is not None else 1
+    ldg = G.shape[1] if G is not None else 1
+    rc = _load().shs_server_submit(srv, sys_id, sh.size, sh.ctypes.data_as(ctypes.c_void_p), mode, outputs,
+                                   _ptr(X), ldx, _ptr(G), ldg, _ptr(eta), _ptr(status), ctypes.byref(rid))
+    _check("shs_server_submit", rc)
+    return rid.value
+
+
+def shs_server_poll(srv, req_id):
+    st = ctypes.c_int()
+    _check("shs_server_poll", _load().shs_server_poll(srv, req_id, ctypes.byref(st)))
+    return st.value
+
+
+def shs_server_wait(srv, req_id, timeout_ms=-1.0):
+    _check("shs_server_wait", _load().shs_server_wait(srv, req_id, float(timeout_ms)))
+
+
+def shs_server_latency(srv, req_id):
+    ms = ctypes.c_double()
+    _check("shs_server_latency", _load().shs_server_latency(srv, req_id, ctypes.byref(ms)))
+    return ms.value
+
+
+def shs_server_stats(srv):
+    st = _ServerStats()
+    _check("shs_server_stats", _load().shs_server_stats(srv, ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in _ServerStats._fields_}
+
+
+def shs_server_destroy(srv):
+    _load().shs_server_destroy(srv)

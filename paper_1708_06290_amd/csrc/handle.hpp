@@ -1,0 +1,53 @@
+// The handle of a reduced system and library-internal helpers shared by
+// the solve path and the serving layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "shiftsolve.h"
+
+struct shs_handle {
+    int64_t n = 0, m = 0, p = 0;
+    int device = 0;
+    int64_t ldh = 0;
+    double *H = nullptr;       // n x n, sign-normalised m-Hessenberg
+    float *H32 = nullptr;      // FP32 copy for the mixed-precision sweep
+    double *Bw = nullptr;      // n x m, R = Q^T B (rows >= m zero)
+    double *Rtop = nullptr;    // m x m leading block of R (ld m)
+    double *rcolmax = nullptr; // max_i |R(i, c)|
+    double *Ct = nullptr;      // p x n, C Q (ld max(1,p))
+    int64_t ldct = 1;
+    double *V = nullptr;       // Householder vectors: column j holds reflector j from row start[j]
+    double *tauv = nullptr;    // n taus (reflectors 0..m-1 of Q_B, then m.. of Q_A)
+    int64_t nrefl = 0;
+    double *sgn = nullptr;     // diagonal signs
+    double *offrow = nullptr;  // off-diagonal row sums of |H|
+    double *diag = nullptr;    // diagonal of H
+    double reduce_ms = 0.0;
+    size_t resident = 0;
+    // phase timing of the last solve (events recorded on the solve's stream)
+    bool timing = false;
+    struct Mark { int phase; int64_t shifts; hipEvent_t a, b; };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> pool;
+    int64_t refine_iterations = 0, fallback_shifts = 0;
+};
+
+enum { PH_SWEEP = 0, PH_QSTAR, PH_RESIDUAL, PH_SWEEP32, PH_SWEEP32D, PH_OTHER, PH_COUNT };
+
+namespace shs {
+
+// FP64 residual R - (H X - sigma X) and backward error of the listed shifts
+// (dlist == nullptr: shifts 0 .. s_list-1); Res optional; resmax/xmax are
+// per-column scratch of m * s_total entries.
+hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const double *shifts, const double *X,
+                   int64_t ldx, double *Res, unsigned long long *resmax, unsigned long long *xmax, double *eta,
+                   int32_t *status, int64_t s_total, hipStream_t st);
+
+// G(:, j*m + c) = Ct X(:, j*m + c) for shifts 0 .. s-1.
+hipError_t g_eval(shs_handle *h, int64_t s, const double *X, int64_t ldx, double *G, int64_t ldg, hipStream_t st);
+
+}  // namespace shs

@@ -8,40 +8,13 @@
 #include <vector>
 
 #include "shiftsolve.h"
+#include "handle.hpp"
 #include "kernels.hpp"
 #include "reduce.hpp"
 #include "residual.hpp"
 
 using namespace shs;
 
-struct shs_handle {
-    int64_t n = 0, m = 0, p = 0;
-    int device = 0;
-    int64_t ldh = 0;
-    double *H = nullptr;       // n x n, sign-normalised m-Hessenberg
-    float *H32 = nullptr;      // FP32 copy for the mixed-precision sweep
-    double *Bw = nullptr;      // n x m, R = Q^T B (rows >= m zero)
-    double *Rtop = nullptr;    // m x m leading block of R (ld m)
-    double *rcolmax = nullptr; // max_i |R(i, c)|
-    double *Ct = nullptr;      // p x n, C Q (ld max(1,p))
-    int64_t ldct = 1;
-    double *V = nullptr;       // Householder vectors: column j holds reflector j from row start[j]
-    double *tauv = nullptr;    // n taus (reflectors 0..m-1 of Q_B, then m.. of Q_A)
-    int64_t nrefl = 0;
-    double *sgn = nullptr;     // diagonal signs
-    double *offrow = nullptr;  // off-diagonal row sums of |H|
-    double *diag = nullptr;    // diagonal of H
-    double reduce_ms = 0.0;
-    size_t resident = 0;
-    // phase timing of the last solve (events recorded on the solve's stream)
-    bool timing = false;
-    struct Mark { int phase; int64_t shifts; hipEvent_t a, b; };
-    std::vector<Mark> marks;
-    std::vector<hipEvent_t> pool;
-    int64_t refine_iterations = 0, fallback_shifts = 0;
-};
-
-enum { PH_SWEEP = 0, PH_QSTAR, PH_RESIDUAL, PH_SWEEP32, PH_SWEEP32D, PH_OTHER, PH_COUNT };
 
 namespace {
 
@@ -212,39 +185,6 @@ __global__ void fill_status_kernel(int count, const int32_t *list, const int32_t
     dst[sid] = (st == 0) ? code : st;
 }
 
-// residual + eta for the listed shifts; Res optional.
-hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const double *shifts, const double *X,
-                   int64_t ldx, double *Res, unsigned long long *resmax, unsigned long long *xmax, double *eta,
-                   int32_t *status, int64_t s_total, hipStream_t st)
-{
-    const int64_t n = h->n, m = h->m;
-    PhaseScope ps(h, PH_RESIDUAL, s_list, st);
-    hipError_t e = hipMemsetAsync(resmax, 0, sizeof(unsigned long long) * m * s_total, st);
-    if (e != hipSuccess) return e;
-    e = hipMemsetAsync(xmax, 0, sizeof(unsigned long long) * m * s_total, st);
-    if (e != hipSuccess) return e;
-    ResidualArgs ra;
-    ra.n = (int)n;
-    ra.m = (int)m;
-    ra.count = (int)s_list;
-    ra.list = dlist;
-    ra.H = h->H;
-    ra.ldh = h->ldh;
-    ra.Rtop = h->Rtop;
-    ra.shifts = shifts;
-    ra.X = X;
-    ra.ldx = ldx;
-    ra.Res = Res;
-    ra.ldr = n;
-    ra.resmax = resmax;
-    ra.xmax = xmax;
-    hipLaunchKernelGGL(residual_kernel, dim3(cdiv(n, 64), cdiv(s_list * m, 32)), dim3(256), 0, st, ra);
-    hipLaunchKernelGGL(eta_kernel, dim3((unsigned)s_list), dim3(256), 0, st, (int)n, (int)m, (int)s_list, dlist,
-                       shifts, (const double *)h->offrow, (const double *)h->diag, (const double *)h->rcolmax,
-                       (const unsigned long long *)resmax, (const unsigned long long *)xmax, eta, status);
-    return hipGetLastError();
-}
-
 // FP64 sweep + Q* pass for the listed shifts into X.
 hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const double *shifts, void *work,
                       const Layout &L, double *X, int64_t ldx, int32_t *status, hipStream_t st)
@@ -294,6 +234,49 @@ hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const 
 }  // namespace
 
 namespace shs {
+
+// residual + eta for the listed shifts; Res optional.
+hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const double *shifts, const double *X,
+                   int64_t ldx, double *Res, unsigned long long *resmax, unsigned long long *xmax, double *eta,
+                   int32_t *status, int64_t s_total, hipStream_t st)
+{
+    const int64_t n = h->n, m = h->m;
+    PhaseScope ps(h, PH_RESIDUAL, s_list, st);
+    hipError_t e = hipMemsetAsync(resmax, 0, sizeof(unsigned long long) * m * s_total, st);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(xmax, 0, sizeof(unsigned long long) * m * s_total, st);
+    if (e != hipSuccess) return e;
+    ResidualArgs ra;
+    ra.n = (int)n;
+    ra.m = (int)m;
+    ra.count = (int)s_list;
+    ra.list = dlist;
+    ra.H = h->H;
+    ra.ldh = h->ldh;
+    ra.Rtop = h->Rtop;
+    ra.shifts = shifts;
+    ra.X = X;
+    ra.ldx = ldx;
+    ra.Res = Res;
+    ra.ldr = n;
+    ra.resmax = resmax;
+    ra.xmax = xmax;
+    hipLaunchKernelGGL(residual_mfma_kernel, dim3(cdiv(n, 128), cdiv(s_list * m, 64)), dim3(256), 0, st, ra);
+    hipLaunchKernelGGL(eta_kernel, dim3((unsigned)s_list), dim3(256), 0, st, (int)n, (int)m, (int)s_list, dlist,
+                       shifts, (const double *)h->offrow, (const double *)h->diag, (const double *)h->rcolmax,
+                       (const unsigned long long *)resmax, (const unsigned long long *)xmax, eta, status);
+    return hipGetLastError();
+}
+
+hipError_t g_eval(shs_handle *h, int64_t s, const double *X, int64_t ldx, double *G, int64_t ldg, hipStream_t st)
+{
+    if (s <= 0 || h->p <= 0) return hipSuccess;
+    hipLaunchKernelGGL(g_eval_kernel, dim3((unsigned)(s * h->m)), dim3(256), 0, st, (int)h->n, (int)h->p, (int)h->m,
+                       (int)s, (const int32_t *)nullptr, (const double *)h->Ct, h->ldct, X, ldx, G, ldg);
+    return hipGetLastError();
+}
+
+
 
 bool sweep_geometry(bool fp32, int m, bool dense, SweepGeometry *g)
 {
@@ -527,9 +510,11 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outp
     const int64_t n = h->n, m = h->m;
     Layout L;
     if (!layout(h, s, mode, outputs, &L)) return SHS_ERR_UNSUPPORTED;
-    h->marks.clear();
-    h->refine_iterations = 0;
-    h->fallback_shifts = 0;
+    if (h->timing) {   // timing state is only touched when enabled (see shs_set_timing)
+        h->marks.clear();
+        h->refine_iterations = 0;
+        h->fallback_shifts = 0;
+    }
     bool owned = false;
     if (work) {
         if (work_bytes < L.total) return -9;
@@ -623,7 +608,7 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outp
             const int64_t nc = (int64_t)active.size();
             e = hipMemcpyAsync(dlist, active.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st);
             if (e != hipSuccess) break;
-            h->refine_iterations++;
+            if (h->timing) h->refine_iterations++;
             {
                 PhaseScope ps(h, PH_OTHER, nc, st);
                 hipLaunchKernelGGL(scale_residual_kernel, dim3(std::max<unsigned>(1, cdiv(n * m, 256 * 16)), (unsigned)nc),
@@ -677,7 +662,7 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outp
         if (e == hipSuccess && !fallback.empty()) {
             // FP64 sweep for the shifts the mixed form could not certify
             const int64_t nf = (int64_t)fallback.size();
-            h->fallback_shifts = nf;
+            if (h->timing) h->fallback_shifts = nf;
             e = hipMemcpyAsync(dlist, fallback.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, st);
             if (e == hipSuccess) e = solve_fp64(h, nf, dlist, shifts, work, L, Xw, ldxw, st2, st);
             if (e == hipSuccess)
@@ -691,10 +676,7 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outp
     }
     if (e == hipSuccess && (outputs & SHS_OUT_G) && h->p > 0) {
         PhaseScope ps(h, PH_OTHER, s, st);
-        hipLaunchKernelGGL(g_eval_kernel, dim3((unsigned)(s * m)), dim3(256), 0, st, (int)n, (int)h->p, (int)m,
-                           (int)s, (const int32_t *)nullptr, (const double *)h->Ct, h->ldct, (const double *)Xw,
-                           ldxw, G, ldg);
-        e = hipGetLastError();
+        e = g_eval(h, s, Xw, ldxw, G, ldg, st);
     }
     if (owned) {
         hipError_t e2 = hipFreeAsync(work, st);

@@ -37,26 +37,18 @@ struct QstarArgs {
     const double *scale;         // per shift id, or nullptr (= 1)
 };
 
+// One lane's share of the Q* pass: column c of one shift.  rf is the
+// shift's reflector store (tile_rows, tile_stride, slot describe its layout),
+// X points at column c of the shift's output block.
 template <typename T, int M, bool DENSE_IN>
-__global__ __launch_bounds__(64) void qstar_kernel(QstarArgs<T> a)
+__device__ __forceinline__ void qstar_body(int n, bool active, int c, const T *rf, int tile_rows,
+                                           int64_t tile_stride, int slot, const T *Y, double *X,
+                                           int accumulate, double sc)
 {
     constexpr int NP = M + 1;
-    constexpr int SPW = kWave / M;
-    const int lane = threadIdx.x;
-    const int sw = lane / M, c = lane % M;
-    const int item = blockIdx.x * SPW + sw;
-    const bool active = (sw < SPW) && (item < a.count);
-    const int sid = active ? (a.list ? a.list[item] : item) : 0;
-    const int n = a.n;
-
-    const T *rf = a.refl + (int64_t)sid * a.refl_stride;
-    const T *Y = a.Y + (int64_t)sid * a.y_stride;
-    double *X = a.X + ((int64_t)sid * M + c) * a.ldx * 2;
-    const double sc = (a.accumulate && a.scale) ? a.scale[sid] : 1.0;
-
     auto slot_ptr = [&](int k) -> const T * {
-        const int t = k / a.tile_rows;
-        return rf + (int64_t)t * a.tile_stride + (int64_t)(k - t * a.tile_rows) * a.slot;
+        const int t = k / tile_rows;
+        return rf + (int64_t)t * tile_stride + (int64_t)(k - t * tile_rows) * slot;
     };
     auto input_row = [&](int i, double &xr, double &xi) {
         xr = 0.0;
@@ -130,7 +122,7 @@ __global__ __launch_bounds__(64) void qstar_kernel(QstarArgs<T> a)
                 const int row = k - M;
                 if (active && row >= 0 && row < n) {
                     double *px = X + 2 * (int64_t)row;
-                    if (a.accumulate) {
+                    if (accumulate) {
                         px[0] += sc * yr[Q];
                         px[1] += sc * yi[Q];
                     } else {
@@ -143,6 +135,22 @@ __global__ __launch_bounds__(64) void qstar_kernel(QstarArgs<T> a)
             }
         });
     }
+}
+
+template <typename T, int M, bool DENSE_IN>
+__global__ __launch_bounds__(64) void qstar_kernel(QstarArgs<T> a)
+{
+    constexpr int SPW = kWave / M;
+    const int lane = threadIdx.x;
+    const int sw = lane / M, c = lane % M;
+    const int item = blockIdx.x * SPW + sw;
+    const bool active = (sw < SPW) && (item < a.count);
+    const int sid = active ? (a.list ? a.list[item] : item) : 0;
+    const T *rf = a.refl + (int64_t)sid * a.refl_stride;
+    const T *Y = a.Y + (int64_t)sid * a.y_stride;
+    double *X = a.X + ((int64_t)sid * M + c) * a.ldx * 2;
+    const double sc = (a.accumulate && a.scale) ? a.scale[sid] : 1.0;
+    qstar_body<T, M, DENSE_IN>(a.n, active, c, rf, a.tile_rows, a.tile_stride, a.slot, Y, X, a.accumulate, sc);
 }
 
 }  // namespace shs

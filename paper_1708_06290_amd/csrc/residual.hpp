@@ -164,6 +164,152 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
     }
 }
 
+typedef double shs_dbl4 __attribute__((ext_vector_type(4)));
+
+// MFMA form of residual_kernel: the product H X runs on the FP64 matrix
+// cores (v_mfma_f64_16x16x4f64).  A workgroup of 4 waves computes 128 rows x
+// 64 complex columns; wave (wr, wc) owns rows wr*64 .. +63 and complex
+// columns wc*32 .. +31 as 4 x 4 MFMA tiles of 16 x 16.  In LDS the X tile
+// keeps, for each group of 16 complex columns, the 16 real parts followed by
+// the 16 imaginary parts, so N-tiles 2q and 2q+1 of a wave hold the real and
+// imaginary parts of the same 16 complex columns and every lane ends with
+// whole complex results.  MFMA operand layout: lane l holds A(l%16, l/16)
+// and B(l/16, l%16); result register r of lane l is D(4 r + l/16, l%16)
+// (checked on the device with a decoding probe).
+__global__ __launch_bounds__(256) void residual_mfma_kernel(ResidualArgs a)
+{
+    constexpr int BM = 128, BNC = 64, BK = 16;
+    __shared__ double Hs[BK][BM];
+    __shared__ double Xs[BK][2 * BNC];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int i0 = blockIdx.x * BM;
+    const int w0 = blockIdx.y * BNC;
+    const int ncols = a.count * a.m;
+    const int n = a.n, m = a.m;
+
+    shs_dbl4 acc[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = shs_dbl4{0.0, 0.0, 0.0, 0.0};
+
+    // loads of this thread: H rows i0 + tid%128, k = k0 + tid/128 + 2e (e < 8);
+    // X row k0 + tid%16 of complex tile columns tid/16 + 16e (e < 4)
+    const double *xcol[4];
+    bool xok[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int w = w0 + tid / 16 + 16 * e;
+        xok[e] = w < ncols;
+        const int ww = xok[e] ? w : 0;
+        const int item = ww / m, c = ww % m;
+        const int sid = a.list ? a.list[item] : item;
+        xcol[e] = a.X + ((int64_t)sid * m + c) * a.ldx * 2;
+    }
+    const int hr = tid % BM, hk = tid / BM;
+    const int xk = tid % BK, xc = tid / BK;
+    double hreg[8], xre[4], xim[4];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int i = i0 + hr, k = k0 + hk + 2 * e;
+            hreg[e] = (i < n && k < n) ? a.H[(int64_t)k * a.ldh + i] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = k0 + xk;
+            const bool ok = xok[e] && k < n;
+            xre[e] = ok ? xcol[e][2 * (int64_t)k] : 0.0;
+            xim[e] = ok ? xcol[e][2 * (int64_t)k + 1] : 0.0;
+        }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Hs[hk + 2 * e][hr] = hreg[e];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int cc = xc + 16 * e, g = cc / 16, j = cc % 16;
+            Xs[xk][32 * g + j] = xre[e];
+            Xs[xk][32 * g + 16 + j] = xim[e];
+        }
+    };
+
+    int kstart = i0 - m;
+    if (kstart < 0) kstart = 0;
+    kstart = (kstart / BK) * BK;
+    gload(kstart);
+    for (int k0 = kstart; k0 < n; k0 += BK) {
+        __syncthreads();
+        lstore();
+        __syncthreads();
+        if (k0 + BK < n) gload(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double af[4], bf[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) af[mt] = Hs[kk + lane / 16][wr * 64 + mt * 16 + lane % 16];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) bf[nt] = Xs[kk + lane / 16][wc * 64 + nt * 16 + lane % 16];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mt], bf[nt], acc[mt][nt], 0, 0, 0);
+        }
+    }
+
+    // epilogue: Res = R - H X + sigma X and column maxima
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int w = w0 + wc * 32 + q * 16 + lane % 16;
+        double mr = 0.0, mx = 0.0;
+        if (w < ncols) {
+            const int item = w / m, c = w % m;
+            const int sid = a.list ? a.list[item] : item;
+            const double sr = a.shifts[2 * sid], si = a.shifts[2 * sid + 1];
+            const int64_t col = (int64_t)sid * m + c;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + wr * 64 + mt * 16 + 4 * r + lane / 16;
+                    if (i < n) {
+                        const double *px = a.X + (col * a.ldx + i) * 2;
+                        const double xr = px[0], xi = px[1];
+                        const double hxr = acc[mt][2 * q][r], hxi = acc[mt][2 * q + 1][r];
+                        const double rr = ((i < m) ? a.Rtop[c * m + i] : 0.0) - hxr + (sr * xr - si * xi);
+                        const double ri = -hxi + (sr * xi + si * xr);
+                        if (a.Res) {
+                            double *pr = a.Res + (col * a.ldr + i) * 2;
+                            pr[0] = rr;
+                            pr[1] = ri;
+                        }
+                        const double ar = hypot(rr, ri), ax = hypot(xr, xi);
+                        mr = (ar > mr || ar != ar) ? ar : mr;
+                        mx = (ax > mx || ax != ax) ? ax : mx;
+                    }
+                }
+        }
+        // lanes l, l+16, l+32, l+48 hold the same column
+#pragma unroll
+        for (int off = 16; off < 64; off <<= 1) {
+            const double orr = __shfl_xor(mr, off), oxx = __shfl_xor(mx, off);
+            mr = (orr > mr || orr != orr) ? orr : mr;
+            mx = (oxx > mx || oxx != oxx) ? oxx : mx;
+        }
+        if (lane < 16 && w < ncols) {
+            const int item = w / m, c = w % m;
+            const int sid = a.list ? a.list[item] : item;
+            const int64_t col = (int64_t)sid * m + c;
+            if (mr != mr) mr = __longlong_as_double(0x7ff8000000000000LL);
+            if (mx != mx) mx = __longlong_as_double(0x7ff8000000000000LL);
+            atomic_max_nonneg(a.resmax + col, mr);
+            atomic_max_nonneg(a.xmax + col, mx);
+        }
+    }
+}
+
 // eta per listed shift; updates status (NaN -> NONFINITE).
 __global__ __launch_bounds__(256) void eta_kernel(int n, int m, int count, const int32_t *list,
                                                   const double *shifts, const double *offrow,

@@ -254,25 +254,40 @@ __device__ __forceinline__ void pivot_row(const T (&wr)[R][M + 1], const T (&wi)
     }
 }
 
+// One shift's sweep: everything one wavefront needs.
+template <typename T>
+struct SweepItem {
+    int n;
+    const T *H;            // column-major n x n
+    int64_t ldh;
+    T sgr, sgi;            // the shift
+    T *rf;                 // this shift's reflector store
+    T *Y;                  // structured: m x m (ld m); dense: n x m (ld n)
+    const T *E;            // dense right-hand side n x m (ld n)
+    const double *Rtop;    // structured: m x m leading block of R (ld m)
+    int32_t *status;       // this shift's status
+};
+
+// LDS a sweep body needs (elements of T): reflector chunk + R_sigma block.
 template <typename T, int M, bool DENSE>
-__global__ __launch_bounds__(64, 2) void sweep_kernel(SweepArgs<T> a)
+__host__ __device__ constexpr int sweep_lds_elems()
+{
+    return SweepShape<T, M, DENSE>::CH + (DENSE ? 2 : 2 * M * M);
+}
+
+template <typename T, int M, bool DENSE>
+__device__ __forceinline__ void sweep_body(const SweepItem<T> &it, T *lds_refl, T *lds_rs)
 {
     using Sh = SweepShape<T, M, DENSE>;
     constexpr int R = Sh::R, TT = Sh::TT, S = Sh::S, EM = Sh::EM, NP = Sh::NP;
     constexpr int KC = Sh::KC, CH = Sh::CH, PL = Sh::PL;
-    __shared__ T lds_refl[CH];
-    __shared__ T lds_rs[DENSE ? 2 : 2 * M * M];   // R_sigma(0:m, 0:m), column k at k*m
-
-    const int item = blockIdx.x;
-    if (item >= a.count) return;
-    const int sid = a.list ? a.list[item] : item;
     const int lane = threadIdx.x;
-    const int n = a.n;
-    const T *H = a.H;
-    const int64_t ldh = a.ldh;
-    const T sgr = (T)a.shifts[2 * sid], sgi = (T)a.shifts[2 * sid + 1];
-    T *rf = a.refl + (int64_t)sid * a.refl_stride;
-    T *Y = a.Y + (int64_t)sid * a.y_stride;
+    const int n = it.n;
+    const T *H = it.H;
+    const int64_t ldh = it.ldh;
+    const T sgr = it.sgr, sgi = it.sgi;
+    T *rf = it.rf;
+    T *Y = it.Y;
     const int64_t tstride = refl_tile_stride<T>(TT, S);
 
     T wr[R][NP], wi[R][NP];
@@ -304,7 +319,7 @@ __global__ __launch_bounds__(64, 2) void sweep_kernel(SweepArgs<T> a)
                 }
             }
             if constexpr (DENSE) {
-                const T *E = a.E + (int64_t)sid * a.e_stride;
+                const T *E = it.E;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int i = lo + r * kWave + lane;
@@ -463,7 +478,7 @@ __global__ __launch_bounds__(64, 2) void sweep_kernel(SweepArgs<T> a)
             const int c = lane;
             T e_r[M], e_i[M];
 #pragma unroll
-            for (int i = 0; i < M; ++i) { e_r[i] = (T)a.Rtop[c * M + i]; e_i[i] = T(0); }
+            for (int i = 0; i < M; ++i) { e_r[i] = (T)it.Rtop[c * M + i]; e_i[i] = T(0); }
 #pragma unroll
             for (int k = M - 1; k >= 0; --k) {
                 const T br = lds_rs[2 * (k * M + k)], bi = lds_rs[2 * (k * M + k) + 1];
@@ -485,7 +500,7 @@ __global__ __launch_bounds__(64, 2) void sweep_kernel(SweepArgs<T> a)
         nonfinite = __any(nonfinite);
     }
 
-    if (lane == 0) a.status[sid] = singular ? 1 : (nonfinite ? 2 : 0);
+    if (lane == 0) *it.status = singular ? 1 : (nonfinite ? 2 : 0);
     if (singular) {
         // no solution exists: NaN outputs for this shift only
         const T qnan = (T)__builtin_nan("");
@@ -495,6 +510,27 @@ __global__ __launch_bounds__(64, 2) void sweep_kernel(SweepArgs<T> a)
             Y[2 * idx + 1] = qnan;
         }
     }
+}
+
+template <typename T, int M, bool DENSE>
+__global__ __launch_bounds__(64, 2) void sweep_kernel(SweepArgs<T> a)
+{
+    __shared__ T lds[sweep_lds_elems<T, M, DENSE>()];
+    const int item = blockIdx.x;
+    if (item >= a.count) return;
+    const int sid = a.list ? a.list[item] : item;
+    SweepItem<T> it;
+    it.n = a.n;
+    it.H = a.H;
+    it.ldh = a.ldh;
+    it.sgr = (T)a.shifts[2 * sid];
+    it.sgi = (T)a.shifts[2 * sid + 1];
+    it.rf = a.refl + (int64_t)sid * a.refl_stride;
+    it.Y = a.Y + (int64_t)sid * a.y_stride;
+    it.E = DENSE ? a.E + (int64_t)sid * a.e_stride : nullptr;
+    it.Rtop = a.Rtop;
+    it.status = a.status + sid;
+    sweep_body<T, M, DENSE>(it, lds, lds + SweepShape<T, M, DENSE>::CH);
 }
 
 }  // namespace shs

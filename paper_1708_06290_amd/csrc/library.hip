@@ -9,6 +9,7 @@
 
 #include "shiftsolve.h"
 #include "handle.hpp"
+#include "gemm.hpp"
 #include "kernels.hpp"
 #include "reduce.hpp"
 #include "residual.hpp"
@@ -319,6 +320,120 @@ bool launch_qstar(int m, bool dense_in, const QstarArgs<float> &a, hipStream_t s
 
 }  // namespace shs
 
+namespace {
+
+constexpr size_t kReducePart = (size_t)1 << 22;   // split-K workspace of the reduction's GEMMs (32 MiB)
+
+// Blocked m-Hessenberg reduction of h->H (after the similarity with Q_B),
+// following Algorithms 2 and 3: panels of b columns, mini-blocks of m.
+//   For a panel starting at column z (reflectors on rows >= r_lo = z + m):
+//   per mini-block q0 .. q0+mb-1 (columns j0 = z + q0 ..):
+//     1. right update by the panel's earlier mini-blocks: A(:, mb cols) -= Y V(mb rows, :)^T
+//     2. left update by the panel's earlier reflectors:  A(r_lo:, mb cols) -= V T^T V^T A(r_lo:, mb cols)
+//     3. the mini-block's own reflectors (miniblock_kernel), its T block
+//     4. T12 = -T_old (V_old^T V_new) T_new
+//     5. Y_new = (A(:, j0+m:) V_new - Y_old (V_old^T V_new)) T_new
+//   then the trailing columns c >= z + b: right A -= Y V^T, left A -= V T^T V^T A,
+//   and C <- C (I - V T V^T).  Y = A V T always refers to the panel-start A;
+//   the columns it reads (>= j0 + m) are still untouched when it is formed.
+hipError_t reduce_blocked(shs_handle *h, double *work, hipStream_t st)
+{
+    const int n = (int)h->n, m = (int)h->m, p = (int)h->p;
+    const int b = std::max(m, (64 / m) * m);
+    double *H = h->H;
+    const int64_t ldh = h->ldh;
+    double *Vp = work;                        // n x b
+    double *Y = Vp + (size_t)n * b;           // n x b
+    double *Z = Y + (size_t)n * b;            // n x m
+    double *Tp = Z + (size_t)n * m;           // b x b
+    double *S = Tp + (size_t)b * b;           // b x m
+    double *U = S + (size_t)b * m;            // b x m
+    double *W = U + (size_t)b * m;            // b x n
+    double *W2 = W + (size_t)b * n;           // b x n
+    double *CV = W2 + (size_t)b * n;          // max(1,p) x b
+    double *CVT = CV + (size_t)std::max(1, p) * b;
+    double *taus = CVT + (size_t)std::max(1, p) * b;   // b
+    double *part = taus + b;                            // split-K partials
+    const int ldp = std::max(1, p);
+    hipError_t e = hipSuccess;
+#define GEMM(...)                                    \
+    do {                                             \
+        e = gemm_f64(__VA_ARGS__, part, kReducePart, st); \
+        if (e != hipSuccess) return e;               \
+    } while (0)
+    const int nref = n - m - 1;   // columns that get a reflector
+    for (int z = 0; z < nref; z += b) {
+        const int bz = std::min(b, nref - z);
+        const int r_lo = z + m, L = n - r_lo;
+        // rows above each vector's first row are read by the GEMMs as zeros
+        e = hipMemsetAsync(Vp, 0, sizeof(double) * n * b, st);
+        if (e != hipSuccess) return e;
+        e = hipMemsetAsync(Tp, 0, sizeof(double) * b * b, st);
+        if (e != hipSuccess) return e;
+        for (int q0 = 0; q0 < bz; q0 += m) {
+            const int mb = std::min(m, bz - q0);
+            const int j0 = z + q0;
+            double *Acols = H + (int64_t)j0 * ldh;
+            if (q0 > 0) {
+                // 1. right update by earlier mini-blocks (all rows)
+                GEMM(false, true, n, mb, q0, -1.0, Y, n, Vp + j0, n, Acols, ldh, true);
+                // 2. left update by earlier reflectors (rows r_lo ..)
+                GEMM(true, false, q0, mb, L, 1.0, Vp + r_lo, n, Acols + r_lo, ldh, S, b, false);
+                GEMM(true, false, q0, mb, q0, 1.0, Tp, b, S, b, U, b, false);
+                GEMM(false, false, L, mb, q0, -1.0, Vp + r_lo, n, U, b, Acols + r_lo, ldh, true);
+            }
+            // 3. this mini-block's reflectors and T block
+            hipLaunchKernelGGL(miniblock_kernel, dim3(1), dim3(1024), 0, st, n, m, r_lo, j0, mb, q0, H, ldh, Vp,
+                               taus, Tp, b);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            const double *Vnew = Vp + (int64_t)q0 * n;
+            if (q0 > 0) {
+                // 4. S = V_old^T V_new; T12 = -T_old S T_new
+                GEMM(true, false, q0, mb, L, 1.0, Vp + r_lo, n, Vnew + r_lo, n, S, b, false);
+                GEMM(false, false, q0, mb, mb, 1.0, S, b, Tp + (int64_t)q0 * b + q0, b, U, b, false);
+                GEMM(false, false, q0, mb, q0, -1.0, Tp, b, U, b, Tp + (int64_t)q0 * b, b, false);
+            }
+            // 5. Y_new = (A(:, j0+m:) V_new - Y_old S) T_new
+            const int c1 = j0 + m;
+            GEMM(false, false, n, mb, n - c1, 1.0, H + (int64_t)c1 * ldh, ldh, Vnew + c1, n, Z, n, false);
+            if (q0 > 0) GEMM(false, false, n, mb, q0, -1.0, Y, n, S, b, Z, n, true);
+            GEMM(false, false, n, mb, mb, 1.0, Z, n, Tp + (int64_t)q0 * b + q0, b, Y + (int64_t)q0 * n, n, false);
+        }
+        // trailing columns
+        const int c0 = z + bz, N = n - c0;
+        if (N > 0) {
+            double *At = H + (int64_t)c0 * ldh;
+            GEMM(false, true, n, N, bz, -1.0, Y, n, Vp + c0, n, At, ldh, true);
+            GEMM(true, false, bz, N, L, 1.0, Vp + r_lo, n, At + r_lo, ldh, W, b, false);
+            GEMM(true, false, bz, N, bz, 1.0, Tp, b, W, b, W2, b, false);
+            GEMM(false, false, L, N, bz, -1.0, Vp + r_lo, n, W2, b, At + r_lo, ldh, true);
+        }
+        if (p > 0) {
+            GEMM(false, false, p, bz, L, 1.0, h->Ct + (int64_t)r_lo * h->ldct, h->ldct, Vp + r_lo, n, CV, ldp, false);
+            GEMM(false, false, p, bz, bz, 1.0, CV, ldp, Tp, b, CVT, ldp, false);
+            GEMM(false, true, p, L, bz, -1.0, CVT, ldp, Vp + r_lo, n, h->Ct + (int64_t)r_lo * h->ldct, h->ldct, true);
+        }
+        // keep the reflectors for Q (apply_q): reflector m + z + q
+        e = hipMemcpyAsync(h->V + (int64_t)(m + z) * n, Vp, sizeof(double) * n * bz, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(h->tauv + m + z, taus, sizeof(double) * bz, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+#undef GEMM
+    return hipGetLastError();
+}
+
+size_t reduce_blocked_work(int64_t n, int64_t m, int64_t p)
+{
+    const int64_t b = std::max(m, (64 / m) * m);
+    return sizeof(double) * ((size_t)(2 * n * b + n * m + b * b + 2 * b * m + 2 * b * n +
+                                      2 * std::max<int64_t>(1, p) * b + b) +
+                             kReducePart);
+}
+
+}  // namespace
+
 #define RETURN_IF_HIP(expr)                                        \
     do {                                                           \
         hipError_t e_ = (expr);                                    \
@@ -377,7 +492,7 @@ int shs_reduce(int64_t n, int64_t m, int64_t p, const double *A, int64_t lda, co
     h->nrefl = m + std::max<int64_t>(0, n - m - 1);
     size_t acc = 0;
     hipError_t e = hipSuccess;
-    double *part = nullptr;
+    double *part = nullptr, *bwork = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
 #define ALLOC(ptr, cnt)                                \
     do {                                               \
@@ -397,6 +512,8 @@ int shs_reduce(int64_t n, int64_t m, int64_t p, const double *A, int64_t lda, co
     ALLOC(h->diag, n);
 #undef ALLOC
     e = hipMalloc((void **)&part, sizeof(double) * (size_t)std::max<int64_t>(n, 1) * cdiv(n, kRightChunk));
+    if (e != hipSuccess) goto fail;
+    e = hipMalloc((void **)&bwork, reduce_blocked_work(n, m, p));
     if (e != hipSuccess) goto fail;
     h->resident = acc;
 
@@ -433,16 +550,9 @@ int shs_reduce(int64_t n, int64_t m, int64_t p, const double *A, int64_t lda, co
         e = two_sided(h, h->H, h->ldh, L, j, 0, v, tau, part, st);
         if (e != hipSuccess) goto fail;
     }
-    // 3.-4. m-Hessenberg reduction, reflector j annihilates H(j+m+1:, j)
-    for (int64_t j = 0; j + m + 1 < n; ++j) {
-        const int64_t r0 = j + m, L = n - r0;
-        const int64_t idx = m + j;
-        double *v = h->V + idx * n + r0;
-        double *tau = h->tauv + idx;
-        hipLaunchKernelGGL(house_kernel, dim3(1), dim3(1024), 0, st, (int)L, h->H + j * h->ldh + r0, v, tau);
-        e = two_sided(h, h->H, h->ldh, L, r0, j + 1, v, tau, part, st);
-        if (e != hipSuccess) goto fail;
-    }
+    // 3.-4. m-Hessenberg reduction, blocked (reflector j annihilates H(j+m+1:, j))
+    e = reduce_blocked(h, bwork, st);
+    if (e != hipSuccess) goto fail;
     // sign normalisation and derived data
     hipLaunchKernelGGL(signs_kernel, dim3(1), dim3(64), 0, st, (int)n, (int)m, (const double *)h->H, h->ldh,
                        (const double *)h->Bw, (int64_t)n, h->sgn);
@@ -467,12 +577,14 @@ int shs_reduce(int64_t n, int64_t m, int64_t p, const double *A, int64_t lda, co
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     hipFree(part);
+    hipFree(bwork);
     *out = h;
     return 0;
 fail:
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     hipFree(part);
+    hipFree(bwork);
     free_handle(h);
     return e == hipErrorOutOfMemory ? SHS_ERR_NOMEM : SHS_ERR_HIP;
 }

@@ -39,10 +39,11 @@ __device__ inline double block_sum(double v, double *scratch)
 __global__ __launch_bounds__(1024) void house_kernel(int L, double *x, double *vout, double *tau)
 {
     __shared__ double scratch[16];
+    // read before the barriers of block_sum: thread 0 overwrites x[0] below
+    const double alpha = x[0];
     double part = 0.0;
     for (int i = 1 + threadIdx.x; i < L; i += blockDim.x) part = fma(x[i], x[i], part);
     const double sig2 = block_sum(part, scratch);
-    const double alpha = x[0];
     if (sig2 == 0.0) {
         for (int i = threadIdx.x; i < L; i += blockDim.x) vout[i] = (i == 0) ? 1.0 : 0.0;
         if (threadIdx.x == 0) *tau = 0.0;
@@ -210,6 +211,153 @@ __global__ __launch_bounds__(256) void copy_complex_kernel(int n, int ncols, con
     const int64_t c = idx / n, i = idx % n;
     dst[(c * ldd + i) * 2] = src[(c * lds + i) * 2];
     dst[(c * ldd + i) * 2 + 1] = src[(c * lds + i) * 2 + 1];
+}
+
+// ---------------------------------------------------------------------------
+// Blocked m-Hessenberg reduction (Algorithms 2 and 3): one panel of b
+// columns at a time, split into mini-blocks of m columns.  Before a
+// mini-block runs, every earlier reflector of the panel has been applied to
+// its columns by GEMMs (from the right: Y V^T with Y = A V T; from the left:
+// (I - V T^T V^T)); this kernel finishes the columns with the mini-block's
+// own reflectors, one column after the other, on a single workgroup.
+//
+// A reflector of the mini-block acts on rows >= its column + m, and the
+// mini-block has at most m columns, so its reflectors never touch its own
+// columns from the right: only the left products are needed here.  Column
+// jj gets them in compact form, x <- x - V_b T_b^T (V_b^T x) with V_b, T_b
+// the mini-block's first jj reflectors and their triangular factor, in
+// three passes over the column:
+//   1. d = V_b^T x;
+//   2. x <- x - V_b (T_b^T d), while summing ||x(r0+1:)||^2 and
+//      e = V_b(r0+1:, :)^T x(r0+1:) (r0 = column + m, the reflector's first row);
+//   3. the reflector v = (1, x(r0+1:) / (alpha - beta)) is written, x becomes
+//      (beta, 0, ...).  Its T column follows from e without another pass:
+//      V_b^T v = V_b(r0, :)^T + e / (alpha - beta).
+//
+//   columns j0 .. j0+mb-1 of A; rows r_lo .. n-1 are the ones the panel's
+//   reflectors touch (r_lo = z + m for the panel starting at column z);
+//   V: the panel's Householder vectors (column-major, ld n, absolute rows,
+//   zeros above each vector's first row; rows < r_lo are not written);
+//   taus: the panel's taus; T: the panel's b x b triangular factor (ld ldt),
+//   of which this kernel writes the diagonal block of the mini-block
+//   (columns q0 .. q0+mb-1).  Launch with 1024 threads.
+constexpr int kMbNv = SHS_MAX_M + 1;
+
+// Sums v[k] over the workgroup for k < cnt (cnt uniform); the totals land in
+// tot[k].  Fixed order, so the result is reproducible.
+__device__ inline void block_sum_multi(const double (&v)[kMbNv], int cnt, double (*red)[kMbNv], double *tot)
+{
+    const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+#pragma unroll
+    for (int k = 0; k < kMbNv; ++k) {
+        if (k < cnt) {
+            double s = v[k];
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            if ((threadIdx.x & 63) == 0) red[w][k] = s;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+        double s = 0.0;
+        for (int i = 0; i < nw; ++i) s += red[i][threadIdx.x];
+        tot[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void miniblock_kernel(int n, int m, int r_lo, int j0, int mb, int q0, double *A,
+                                                         int64_t lda, double *V, double *taus, double *T, int ldt)
+{
+    __shared__ double red[16][kMbNv];
+    __shared__ double tot[kMbNv];
+    __shared__ double Ts[SHS_MAX_M][SHS_MAX_M];   // Ts[l][k] = T(q0 + l, q0 + k)
+    __shared__ double wv[SHS_MAX_M];
+    __shared__ double s_alpha;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const double *Vb = V + (int64_t)q0 * n;
+    for (int e = tid; e < SHS_MAX_M * SHS_MAX_M; e += nt) Ts[e / SHS_MAX_M][e % SHS_MAX_M] = 0.0;
+    __syncthreads();
+    for (int jj = 0; jj < mb; ++jj) {
+        const int j = j0 + jj, r0 = j + m;
+        double *x = A + (int64_t)j * lda;
+        // 1. d = V_b^T x, then w = T_b^T d
+        if (jj > 0) {
+            double d[kMbNv] = {};
+            for (int i = r_lo + tid; i < n; i += nt) {
+                const double xi = x[i];
+#pragma unroll
+                for (int l = 0; l < SHS_MAX_M; ++l)
+                    if (l < jj) d[l] = fma(Vb[(int64_t)l * n + i], xi, d[l]);
+            }
+            block_sum_multi(d, jj, red, tot);
+            if (tid < jj) {
+                double s = 0.0;
+                for (int k = 0; k <= tid; ++k) s = fma(Ts[k][tid], tot[k], s);
+                wv[tid] = s;
+            }
+            __syncthreads();
+        }
+        // 2. x <- x - V_b w; sig2 = ||x(r0+1:)||^2 and e = V_b(r0+1:, :)^T x(r0+1:)
+        double acc[kMbNv] = {};
+        for (int i = r_lo + tid; i < n; i += nt) {
+            double xi = x[i];
+            if (jj > 0) {
+#pragma unroll
+                for (int l = 0; l < SHS_MAX_M; ++l)
+                    if (l < jj) xi = fma(-wv[l], Vb[(int64_t)l * n + i], xi);
+                x[i] = xi;
+            }
+            if (i == r0) s_alpha = xi;
+            if (i > r0) {
+                acc[0] = fma(xi, xi, acc[0]);
+#pragma unroll
+                for (int l = 0; l < SHS_MAX_M; ++l)
+                    if (l < jj) acc[1 + l] = fma(Vb[(int64_t)l * n + i], xi, acc[1 + l]);
+            }
+        }
+        block_sum_multi(acc, jj + 1, red, tot);
+        const double sig2 = tot[0];
+        const double alpha = s_alpha;
+        double *vout = V + (int64_t)(q0 + jj) * n;
+        double tau = 0.0, scal = 0.0;
+        // 3. the reflector and the new column
+        if (sig2 == 0.0) {
+            for (int i = r_lo + tid; i < n; i += nt) vout[i] = (i == r0) ? 1.0 : 0.0;
+        } else {
+            const double nu = sqrt(fma(alpha, alpha, sig2));
+            const double beta = alpha >= 0.0 ? -nu : nu;
+            scal = 1.0 / (alpha - beta);
+            tau = (beta - alpha) / beta;
+            for (int i = r_lo + tid; i < n; i += nt) {
+                if (i < r0) {
+                    vout[i] = 0.0;
+                } else if (i == r0) {
+                    vout[i] = 1.0;
+                    x[i] = beta;
+                } else {
+                    vout[i] = x[i] * scal;
+                    x[i] = 0.0;
+                }
+            }
+        }
+        // T column: T(l, jj) = -tau sum_{l <= k < jj} T(l, k) (v_k . v),  T(jj, jj) = tau
+        if (tid < jj) wv[tid] = Vb[(int64_t)tid * n + r0] + scal * tot[1 + tid];   // v_tid . v
+        __syncthreads();
+        if (tid < jj) {
+            double s = 0.0;
+            for (int k = tid; k < jj; ++k) s = fma(Ts[tid][k], wv[k], s);
+            Ts[tid][jj] = -tau * s;
+        }
+        if (tid == 0) {
+            taus[q0 + jj] = tau;
+            Ts[jj][jj] = tau;
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < mb * mb; e += nt) {
+        const int l = e % mb, k = e / mb;
+        T[(int64_t)(q0 + k) * ldt + q0 + l] = Ts[l][k];
+    }
 }
 
 }  // namespace shs

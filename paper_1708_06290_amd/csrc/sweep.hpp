@@ -114,15 +114,24 @@ __device__ __forceinline__ const T *refl_slot(const T *rf, int k, int tt, int64_
     return rf + (int64_t)t * tstride + (int64_t)(k - t * tt) * S;
 }
 
-// Fresh column `col` of H for this lane's rows (0 if col < 0 or past n).
+// Fresh column `col` of H for this lane's rows (0 if col < 0).  Rows past n
+// (the ragged bottom tile) read row n-1 instead: they are never pivots and
+// never feed another row, so their values do not matter, and the loads stay
+// free of per-lane branches.
 template <typename T, int R>
 __device__ __forceinline__ void load_fresh(const T *H, int64_t ldh, int n, int lo, int lane, int col,
                                            T (&fr)[R])
 {
+    if (col < 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) fr[r] = T(0);
+        return;
+    }
+    const T *cp = H + (int64_t)col * ldh;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = lo + r * kWave + lane;
-        fr[r] = (col >= 0 && i < n) ? H[(int64_t)col * ldh + i] : T(0);
+        fr[r] = cp[i < n ? i : n - 1];
     }
 }
 
@@ -209,9 +218,14 @@ __device__ __forceinline__ void apply_step(T (&wr)[R][M + 1], T (&wi)[R][M + 1],
             }
             if (r == 0) { d0r = xr; d0i = xi; }
         }
-        const bool dg = (lo + r * kWave + lane) == fcol;
-        wr[r][pm] = dg ? fr[r] - sgr : fr[r];
-        wi[r][pm] = dg ? -sgi : T(0);
+        if (fcol >= lo && fcol < lo + R * kWave) {   // uniform: a diagonal entry enters
+            const bool dg = (lo + r * kWave + lane) == fcol;
+            wr[r][pm] = dg ? fr[r] - sgr : fr[r];
+            wi[r][pm] = dg ? -sgi : T(0);
+        } else {
+            wr[r][pm] = fr[r];
+            wi[r][pm] = T(0);
+        }
     }
 }
 
@@ -342,13 +356,17 @@ __device__ __forceinline__ void sweep_body(const SweepItem<T> &it, T *lds_refl, 
             const int k_hi = n - 1, k_lo = hi;
             int kb = (k_hi / KC) * KC;
             T pre[PL];
+            // slots outside [k_lo, k_hi] are loaded from a clamped (valid)
+            // address and never read back
             auto fetch = [&](int base) {
 #pragma unroll
                 for (int e = 0; e < PL; ++e) {
-                    const int idx = e * kWave + lane;
+                    const int idx0 = e * kWave + lane;
+                    const int idx = idx0 < CH ? idx0 : CH - 1;
                     const int ks = idx / S, el = idx - ks * S;
-                    const int k = base + ks;
-                    pre[e] = (idx < CH && k >= k_lo && k <= k_hi) ? refl_slot(rf, k, TT, tstride, S)[el] : T(0);
+                    int k = base + ks;
+                    k = k < k_lo ? k_lo : (k > k_hi ? k_hi : k);
+                    pre[e] = refl_slot(rf, k, TT, tstride, S)[el];
                 }
             };
             fetch(kb);

@@ -11,7 +11,8 @@ solve of all shifts with the backward error of every shift certified:
 
 The one-time controller-Hessenberg reduction is timed separately.  Inputs
 are resident in HBM before the timed region.  The JSON line also carries the
-roofline of the dominant kernel (the FP64 sweep, FP64-vector-ALU bound) and
+roofline of the dominant kernel (the one with the largest time per step among
+the blocked sweep's update GEMM and tile kernel and the FP64 residual) and
 the oracle timed on this host's cores on a bounded sample of shifts.
 """
 from __future__ import annotations
@@ -44,6 +45,39 @@ def sweep_flops(n: int, m: int) -> float:
     summing k over the n steps gives (16m+4) n^2 / 2.
     """
     return (8.0 * m + 2.0) * n * n
+
+
+def tile_rows(m: int) -> int:
+    """Row-tile height of the FP64 sweep kernels: 64 lanes x rows per lane,
+    where a lane keeps 144 VGPRs of window (2(m+1) doubles per row)."""
+    return 64 * max(1, min(8, 144 // (4 * (m + 1))))
+
+
+def blocked_flops(n: int, m: int):
+    """Algorithmic flops of one shift in the blocked FP64 sweep, split into
+    the per-shift tile kernels and the all-shift update GEMMs.
+
+    Tile kernel of rows lo..hi-1: step k updates the k - lo tile rows above
+    it (16m+4 flops each, as in the unblocked sweep), and forming the block
+    transform applies the tile's n_b reflectors to m columns of length m+1
+    (16(m+1) flops per column and reflector).  Update of the rows above the
+    tile: real H(0:lo, K columns) times 2m real columns per shift (2 lo K 2m
+    flops), plus the carried part z M2 (2 lo (2m)^2) for all but the bottom
+    tile, whose K includes the m carried columns."""
+    tr = tile_rows(m)
+    ntiles = (n + tr - 1) // tr
+    tile = upd = 0.0
+    for t in range(ntiles - 1, -1, -1):
+        lo, hi = t * tr, min(n, (t + 1) * tr)
+        nb = hi - lo
+        tile += (16 * m + 4) * nb * (nb - 1) / 2.0
+        if t == 0:
+            continue
+        tile += 16.0 * (m + 1) * m * nb
+        bottom = t == ntiles - 1
+        K = nb + m if bottom else nb
+        upd += 2.0 * lo * K * 2 * m + (0.0 if bottom else 2.0 * lo * (2 * m) ** 2)
+    return tile, upd
 
 
 def residual_flops(n: int, m: int) -> float:
@@ -144,6 +178,7 @@ def main():
             "certified": bool((e <= 1e-13).all()),
             "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
             "phase_ms_per_step": {k: v / args.steps for k, v in phase.items() if k.endswith("_ms")},
+            "launches_per_step": {k: v / args.steps for k, v in phase.items() if k.endswith("_calls")},
             "refine_iterations": phase.get("refine_iterations", 0) / args.steps,
             "fallback_shifts": phase.get("fallback_shifts", 0) / args.steps,
         }
@@ -151,18 +186,33 @@ def main():
         del work
         torch.cuda.empty_cache()
 
-    # roofline of the dominant kernel: the FP64 sweep (FP64 vector ALU)
+    # roofline of the dominant kernel (largest time per step) of the FP64
+    # form, and of the other two big ones beside it.  Each kernel's time is
+    # the sum of its launches, from HIP events on the solve stream.
     roof = None
+    kernels = {}
     if "fp64" in results:
         r = results["fp64"]
-        sweep_ms = r["phase_ms_per_step"].get("sweep_ms", 0.0)
-        if sweep_ms > 0:
-            achieved = sweep_flops(n, m) * s / (sweep_ms * 1e-3) / 1e12
-            roof = {"bound": "alu", "kernel": f"sweep_kernel<double,{m},false>",
-                    "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                    "avg_launch_ms": round(sweep_ms, 3),
-                    "flops_per_launch": sweep_flops(n, m) * s}
+        ph, calls = r["phase_ms_per_step"], r["launches_per_step"]
+        tile_f, upd_f = blocked_flops(n, m)
+        w = 2 if m <= 1 else 4 if m <= 2 else 8 if m <= 4 else 16 if m <= 8 else 32
+        cand = [
+            (f"zupd_kernel<{w}>", "mfma", ph.get("sweep_update_ms", 0.0), calls.get("sweep_update_calls", 0), upd_f * s),
+            (f"blk_tri_kernel<{m}>", "alu", ph.get("sweep_tile_ms", 0.0), calls.get("sweep_tile_calls", 0), tile_f * s),
+            ("residual_mfma_kernel", "mfma", ph.get("residual_ms", 0.0), calls.get("residual_calls", 0),
+             residual_flops(n, m) * s),
+        ]
+        for name, bound, ms, nl, fl in cand:
+            if ms <= 0 or nl <= 0:
+                continue
+            achieved = fl / (ms * 1e-3) / 1e12
+            kernels[name] = {"bound": bound, "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                             "ms_per_step": round(ms, 3), "launches_per_step": nl,
+                             "avg_launch_ms": round(ms / nl, 4), "flops_per_launch": fl / nl}
+        if kernels:
+            top = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+            roof = {"kernel": top, **kernels[top]}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -190,6 +240,7 @@ def main():
                    "n": n, "m": m, "p": p, "shifts": s, "form": "fp64 sweep, eta certified",
                    "reduce_ms": round(info["reduce_ms"], 1)},
         "roofline": roof,
+        "kernels": kernels,
         "cpu_baseline": cpu,
         "fp64": results.get("fp64"),
         "mixed": results.get("mixed"),
@@ -241,31 +292,32 @@ def serving_leg(args):
                "batches": st["batches"], "max_batch_systems": st["max_batch_systems"],
                "failed": st["failed"], "uncertified": bad}
         print(f"# serving {label}: {out}", file=sys.stderr, flush=True)
-        return out, handles, srv
+        return out, handles, srv, ids
 
     nreq = args.serve_requests
     burst = workloads.request_stream(min(nreq, 64), rate_hz=1e9, seed=workloads.ARRIVAL_SEED + 1)
-    cal, _, srv = run(burst, None, "burst")
+    cal, _, srv, _ = run(burst, None, "burst")
     srv.close()
     cap = cal["requests"] / cal["wall_s"]
     levels = {}
     keep = None
     for frac in (0.5, 0.8):
         reqs = workloads.request_stream(nreq, rate_hz=frac * cap, seed=workloads.ARRIVAL_SEED)
-        res, handles, srv = run(reqs, frac * cap, f"{int(frac * 100)}%")
+        res, handles, srv, ids = run(reqs, frac * cap, f"{int(frac * 100)}%")
         levels[f"load_{int(frac * 100)}"] = res
         if keep is None:
-            keep = (handles[:6], srv)
+            keep = (handles[:6], srv, ids)
         else:
             srv.close()
-    # the same requests alone: FP64 results must be bitwise equal to the mix
-    handles, srv = keep
+    # the same requests alone on the idle server: FP64 results must be
+    # bitwise equal to the mix
+    handles, srv, ids = keep
     same = 0
     checked = 0
     for (h, sys_id, shifts, mode) in handles:
         if mode != "fp64":
             continue
-        alone = systems[sys_id].solve(shifts)
+        alone = srv.wait(srv.submit(ids[sys_id], shifts, mode=ss.SHS_MODE_FP64), timeout_ms=600000)
         torch.cuda.synchronize()
         checked += 1
         same += int(torch.equal(alone.X, h.X.t()))

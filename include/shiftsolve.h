@@ -201,6 +201,13 @@ typedef struct shs_timings_t {
     int64_t sweep32_dense_shifts; /* shift-solves processed by FP32 dense sweeps */
     int64_t refine_iterations;    /* correction rounds run by the mixed mode */
     int64_t fallback_shifts;      /* shifts the mixed mode recomputed in FP64 */
+    /* The FP64 sweep of shs_solve runs blocked by row tiles (Section 3.1,
+     * Step 2 revisited): per tile, one kernel makes the reflectors and the
+     * block transform of every shift, one GEMM updates all rows above for all
+     * shifts.  Both are part of sweep_ms; these split it. */
+    double sweep_tile_ms;         /* per-shift row-tile kernels */
+    double sweep_update_ms;       /* all-shift update GEMMs */
+    int64_t sweep_tile_calls, sweep_update_calls;
 } shs_timings_t;
 
 int shs_set_timing(shs_handle *h, int enable);

@@ -53,7 +53,9 @@ class _Timings(ctypes.Structure):
                [(f, ctypes.c_int64) for f in ("sweep_calls", "qstar_calls", "residual_calls", "sweep32_calls",
                                               "sweep32_dense_calls", "other_calls", "sweep_shifts",
                                               "sweep32_shifts", "sweep32_dense_shifts", "refine_iterations",
-                                              "fallback_shifts")]
+                                              "fallback_shifts")] + \
+               [(f, ctypes.c_double) for f in ("sweep_tile_ms", "sweep_update_ms")] + \
+               [(f, ctypes.c_int64) for f in ("sweep_tile_calls", "sweep_update_calls")]
 
 
 class _ServerConfig(ctypes.Structure):

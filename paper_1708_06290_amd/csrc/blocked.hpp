@@ -1,0 +1,370 @@
+// Blocked FP64 sweep: Step 2 of Section 3.1 done once per row tile for all
+// shifts together, as the paper's "Step 2, revisited" does per block.
+//
+// The per-shift sweep (sweep.hpp) walks every row above a pivot through every
+// reflector.  Grouping the n_b = 64 R steps of one row tile (rows lo .. hi-1)
+// into one block transform P_blk = P_{hi-1} ... P_lo (of size n_b + m, acting
+// on window columns lo-m .. hi-1) changes the update of every row i < lo into
+//
+//   z_i <- [ H(i, lo-m .. hi-1-m)  z_i ] * M_blk,      M_blk = P_blk(:, 0:m),
+//
+// where z_i (m complex values) are row i's carried window columns: before
+// the tile they are columns hi-m .. hi-1, after it columns lo-m .. lo-1.  The
+// first n_b rows of M_blk (M1) multiply the fresh columns of H, which are
+// real and the same for every shift; the last m rows (M2) multiply z_i.  So
+// the update of all rows above the tile, for all shifts, is ONE real GEMM
+// H(0:lo, lo-m : hi-m) * [Re M1 | Im M1 for every shift] on the FP64 matrix
+// cores, plus a per-shift (2m x 2m) product with z.  The shift enters only
+// through the diagonal entries H(i, i) - sigma of the m rows i = lo-m .. lo-1,
+// whose diagonal lies in the block: those rows get -sigma M1(i - lo + m, :).
+//
+// Per row tile, bottom to top:
+//   blk_tri_kernel  one wavefront per shift: loads the tile's window (carried
+//                   columns from Z, fresh columns from H), produces the tile's
+//                   reflectors with the same code as the per-shift sweep
+//                   (stored for the Q* pass), then forms M_blk by applying
+//                   them to [I_m; 0] (lanes c < m, one column each, a sliding
+//                   (m+1)-row window) and writes it real-ified for the GEMM.
+//   zupd_kernel     the GEMM above for rows 0 .. lo-1, in place on Z.
+// The top tile's kernel ends with the m x m back substitution, as before.
+//
+// Z holds, for work item (shift) w, the carried columns of every row as 2m
+// real columns w W .. w W + 2m - 1 (real parts, then imaginary parts) of a
+// column-major n x (W items) array; W, the per-shift column stride, is 2m
+// rounded up to a power of two (>= 2), so a 16-column MFMA block holds one
+// shift (W = 16), half of one (W = 32) or several whole ones (W < 16).  The
+// GEMM never mixes columns, so a shift's values, finite or not, stay in its
+// own columns.  The bottom tile's carried columns are
+// plain columns of H - sigma I, so its GEMM folds them into K (K = n_b + m)
+// and reads no Z.
+#pragma once
+
+#include "sweep.hpp"
+
+namespace shs {
+
+__host__ __device__ constexpr int blk_width(int m)
+{
+    return m <= 1 ? 2 : (m <= 2 ? 4 : (m <= 4 ? 8 : (m <= 8 ? 16 : 32)));
+}
+
+struct BlkTriArgs {
+    int n;
+    int count;                 // work items (= launched workgroups)
+    int t, ntiles;             // this row tile, number of row tiles
+    const double *H;
+    int64_t ldh;
+    const double *shifts;      // interleaved complex, by shift id
+    const int32_t *list;       // work item -> shift id (nullptr = identity)
+    const double *Rtop;        // m x m upper triangle of R (ld m)
+    double *refl;              // per shift id reflector store
+    int64_t refl_stride;
+    double *Y;                 // per shift id m x m complex
+    int64_t y_stride;
+    int32_t *status;           // per shift id
+    const double *Z;           // carried columns (see above), ld ldz
+    int64_t ldz;
+    double *Bm;                // M1 (and for the bottom tile M2) rows, column-major, ld ldb
+    int64_t ldb;
+    double *M2;                // per work item W x W real (row-major), non-bottom tiles
+};
+
+template <int M>
+__global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
+{
+    using T = double;
+    using Sh = SweepShape<T, M, false>;
+    constexpr int R = Sh::R, TT = Sh::TT, S = Sh::S, NP = Sh::NP;
+    constexpr int W = blk_width(M);
+    __shared__ T lds_rs[2 * M * M];
+    const int item = blockIdx.x;
+    if (item >= a.count) return;
+    const int sid = a.list ? a.list[item] : item;
+    const int lane = threadIdx.x;
+    const int n = a.n, t = a.t;
+    const int lo = t * TT, hi = min(n, lo + TT);
+    const bool bottom = t == a.ntiles - 1;
+    const T sgr = a.shifts[2 * sid], sgi = a.shifts[2 * sid + 1];
+    T *rf = a.refl + (int64_t)sid * a.refl_stride;
+    T *Y = a.Y + (int64_t)sid * a.y_stride;
+    const int64_t tstride = refl_tile_stride<T>(TT, S);
+    const double *H = a.H;
+    const int64_t ldh = a.ldh;
+
+    // ---- window at step hi-1: slot p holds position j = (p - (hi-1)) mod (m+1),
+    // column hi-1-m+j.  Position 0 is the fresh column hi-1-m (from H); the
+    // others are the carried columns hi-m .. hi-1 (from Z, or from H for the
+    // bottom tile).  Rows past n only exist in the bottom tile.
+    T wr[R][NP], wi[R][NP], er[R][1], ei[R][1];
+    {
+        const int q0 = (hi - 1) % NP;
+        const double *Zi = a.Z + (int64_t)item * W * a.ldz;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int j = (p - q0 + NP) % NP;
+            const int col = hi - 1 - M + j;
+            if (bottom || j == 0) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = lo + r * kWave + lane;
+                    const T v = (col >= 0 && i < n) ? H[(int64_t)col * ldh + i] : T(0);
+                    const bool dg = i == col;
+                    wr[r][p] = dg ? v - sgr : v;
+                    wi[r][p] = dg ? -sgi : T(0);
+                }
+            } else {
+                const double *zr = Zi + (int64_t)(j - 1) * a.ldz;
+                const double *zi = Zi + (int64_t)(M + j - 1) * a.ldz;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = lo + r * kWave + lane;
+                    wr[r][p] = zr[i];
+                    wi[r][p] = zi[i];
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) { er[r][0] = T(0); ei[r][0] = T(0); }
+    }
+
+    bool singular = false, nonfinite = false;
+    tri_phase<T, M, false>(n, lo, hi, lane, H, ldh, sgr, sgi, rf, tstride, Y, lds_rs, wr, wi, er, ei, singular,
+                           nonfinite);
+    // the tile's reflector stores complete before they are read back below
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+
+    if (t == 0) {
+        // earlier tiles recorded a singular step in the status word
+        const bool before = !bottom && a.status[sid] == 1;
+        finish_shift<T, M, false>(n, lane, a.Rtop, Y, lds_rs, a.status + sid, singular || before, nonfinite);
+        return;
+    }
+    if (lane == 0 && (bottom || singular)) a.status[sid] = singular ? 1 : 0;
+
+    // ---- M_blk = P_{hi-1} ... P_lo [I_m; 0]: lane c < m owns column c ----------
+    // P_k acts on rows k-lo .. k-lo+m of M_blk.  Applied from P_lo upwards, row
+    // p is final once P_{lo+p} is done, so each lane keeps a window of m+1
+    // rows (row p in slot p mod (m+1)), emits the finished row and lets the
+    // next (zero) row in.
+    if (lane < M) {
+        const int c = lane;
+        const int nb = hi - lo;
+        const int K = bottom ? nb + M : nb;
+        double *bcr = a.Bm + (int64_t)(item * W + c) * a.ldb;
+        double *bci = a.Bm + (int64_t)(item * W + M + c) * a.ldb;
+        double *m2 = a.M2 + (int64_t)item * W * W;
+        auto emit = [&](int p, T xr, T xi) {
+            if (p < K) {
+                bcr[p] = xr;
+                bci[p] = xi;
+            } else {
+                // real form of z M2: [zr zi] [[Re, Im], [-Im, Re]]
+                const int cp = p - nb;
+                m2[cp * W + c] = xr;
+                m2[cp * W + M + c] = xi;
+                m2[(M + cp) * W + c] = -xi;
+                m2[(M + cp) * W + M + c] = xr;
+            }
+        };
+        T ur[NP], ui[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) { ur[p] = p == c ? T(1) : T(0); ui[p] = T(0); }
+        for (int kb = lo; kb < hi; kb += NP) {
+            static_for<NP>([&](auto sc) {
+                constexpr int st = decltype(sc)::value;
+                const int k = kb + st;
+                if (k < hi) {
+                    const T *pv = refl_slot<T>(rf, k, TT, tstride, S);
+                    const T tau = pv[0];
+                    T vr[M], vi[M];
+#pragma unroll
+                    for (int j = 0; j < M; ++j) { vr[j] = pv[2 + 2 * j]; vi[j] = pv[3 + 2 * j]; }
+                    // s = v^* u over positions j = 0 .. m (v_m = 1); position j in slot (st + j) mod (m+1)
+                    T sr = ur[(st + M) % NP], si = ui[(st + M) % NP];
+#pragma unroll
+                    for (int j = 0; j < M; ++j) {
+                        const int q = (st + j) % NP;
+                        sr = fma(vr[j], ur[q], fma(vi[j], ui[q], sr));
+                        si = fma(vr[j], ui[q], fma(-vi[j], ur[q], si));
+                    }
+                    const T tr = tau * sr, ti = tau * si;
+#pragma unroll
+                    for (int j = 0; j < M; ++j) {
+                        const int q = (st + j) % NP;
+                        ur[q] = fma(-vr[j], tr, fma(vi[j], ti, ur[q]));
+                        ui[q] = fma(-vr[j], ti, fma(-vi[j], tr, ui[q]));
+                    }
+                    ur[(st + M) % NP] -= tr;
+                    ui[(st + M) % NP] -= ti;
+                    emit(k - lo, ur[st], ui[st]);
+                    ur[st] = T(0);
+                    ui[st] = T(0);
+                }
+            });
+        }
+        // rows nb .. nb+m-1 are still in the window (row nb+m is the zero row)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int p = nb + ((q - nb % NP) + NP) % NP;
+            if (p < nb + M) emit(p, ur[q], ui[q]);
+        }
+    }
+}
+
+struct ZupdArgs {
+    int lo;                    // rows 0 .. lo-1 are updated
+    int c0;                    // first column of H in the block (lo - m)
+    int K;                     // rows of M_blk multiplying H (n_b, or n_b + m for the bottom tile)
+    int m;
+    int ncols;                 // columns of Z (W per work item, a multiple of 128)
+    int count;                 // work items
+    int has_zin;               // 0 for the bottom tile (no carried columns in Z yet)
+    const double *H;
+    int64_t ldh;
+    const double *Bm;
+    int64_t ldb;
+    const double *M2;
+    double *Z;
+    int64_t ldz;
+    const double *shifts;
+    const int32_t *list;
+};
+
+typedef double zupd_dbl4 __attribute__((ext_vector_type(4)));
+
+// Z(0:lo, :) <- H(0:lo, c0 : c0+K) Bm(0:K, :) + (per shift) Z M2, minus
+// sigma M1 on the rows whose diagonal is in the block.  128 x 128 tiles,
+// 4 waves of 64 x 64 (4 x 4 blocks of v_mfma_f64_16x16x4f64; lane l holds
+// A(l%16, l/16), B(l/16, l%16); result register r of lane l is
+// D(4r + l/16, l%16)).  A workgroup reads only its own tile of Z, and every
+// read of Z precedes every write in each wave, so the update is in place.
+template <int W>
+__global__ __launch_bounds__(256) void zupd_kernel(ZupdArgs a)
+{
+    constexpr int BM = 128, BN = 128, BK = 16;
+    __shared__ double As[BK][BM];
+    __shared__ double Bs[BK][BN];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
+    const int lo = a.lo, K = a.K;
+    const double *Ab = a.H + (int64_t)a.c0 * a.ldh;
+
+    zupd_dbl4 acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = zupd_dbl4{0.0, 0.0, 0.0, 0.0};
+
+    double ra[8], rb[8];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int i = i0 + (tid % BM), k = k0 + tid / BM + 2 * e;
+            ra[e] = (i < lo && k < K) ? Ab[(int64_t)k * a.ldh + i] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + (tid % BK), j = j0 + tid / BK + 16 * e;
+            rb[e] = k < K ? a.Bm[(int64_t)j * a.ldb + k] : 0.0;
+        }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) As[tid / BM + 2 * e][tid % BM] = ra[e];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Bs[tid % BK][tid / BK + 16 * e] = rb[e];
+        __syncthreads();
+        if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double af[4], bf[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) af[mt] = As[kk + lane / 16][wr * 64 + mt * 16 + lane % 16];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) bf[nt] = Bs[kk + lane / 16][wc * 64 + nt * 16 + lane % 16];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mt], bf[nt], acc[mt][nt], 0, 0, 0);
+        }
+    }
+
+    // ---- carried part: Z(rows, shift) * M2(shift) -----------------------------
+    // W >= 16: every 16-column block belongs to one shift, so the product is
+    // MFMA work on the block (K = W).  Narrower shifts share a block; there the
+    // product runs on the vector ALU in the epilogue, so that values of one
+    // shift never meet another shift's zeros (a non-finite shift stays
+    // confined to its own columns).
+    if constexpr (W >= 16) {
+        if (a.has_zin) {
+        constexpr int KZ = W;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int cb = j0 + wc * 64 + nt * 16;   // first output column of the block
+            const int sh = cb / W, half = cb % W;
+            double bz[KZ / 4];
+#pragma unroll
+            for (int s = 0; s < KZ / 4; ++s) {
+                const int k = 4 * s + lane / 16, q = lane % 16;
+                bz[s] = a.M2[(int64_t)sh * W * W + k * W + half + q];
+            }
+            const int zc = sh * W;   // first Z column of the shift
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int i = i0 + wr * 64 + mt * 16 + lane % 16;
+#pragma unroll
+                for (int s = 0; s < KZ / 4; ++s) {
+                    const int k = 4 * s + lane / 16;
+                    const double az = i < lo ? a.Z[(int64_t)(zc + k) * a.ldz + i] : 0.0;
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, bz[s], acc[mt][nt], 0, 0, 0);
+                }
+            }
+        }
+        }
+    }
+
+    // ---- epilogue: sigma on the block's diagonal rows, store ----------------
+    const int m = a.m;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wr * 64 + mt * 16 + 4 * r + lane / 16;
+                const int j = j0 + wc * 64 + nt * 16 + lane % 16;
+                if (i >= lo) continue;
+                double v = acc[mt][nt][r];
+                if constexpr (W < 16) {
+                    // every read of Z(i, shift) in this wave happens in the
+                    // iteration that writes Z(i, shift): rows 4r .. 4r+3 of
+                    // the block, all 16 columns
+                    if (a.has_zin) {
+                        const int w = j / W, q = j % W;
+                        const double *zrow = a.Z + (int64_t)w * W * a.ldz + i;
+                        const double *mq = a.M2 + (int64_t)w * W * W + q;
+#pragma unroll
+                        for (int k = 0; k < W; ++k) v = fma(zrow[(int64_t)k * a.ldz], mq[k * W], v);
+                    }
+                }
+                if (i >= lo - m) {
+                    const int w = j / W, q = j % W;
+                    if (w < a.count && q < 2 * m) {
+                        const int sid = a.list ? a.list[w] : w;
+                        const double sr = a.shifts[2 * sid], si = a.shifts[2 * sid + 1];
+                        const int c = q < m ? q : q - m;
+                        const int p = i - (lo - m);
+                        const double ur = a.Bm[(int64_t)(w * W + c) * a.ldb + p];
+                        const double ui = a.Bm[(int64_t)(w * W + m + c) * a.ldb + p];
+                        v -= q < m ? (sr * ur - si * ui) : (sr * ui + si * ur);
+                    }
+                }
+                a.Z[(int64_t)j * a.ldz + i] = v;
+            }
+}
+
+}  // namespace shs

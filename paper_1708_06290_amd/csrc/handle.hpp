@@ -36,7 +36,7 @@ struct shs_handle {
     int64_t refine_iterations = 0, fallback_shifts = 0;
 };
 
-enum { PH_SWEEP = 0, PH_QSTAR, PH_RESIDUAL, PH_SWEEP32, PH_SWEEP32D, PH_OTHER, PH_COUNT };
+enum { PH_SWEEP = 0, PH_QSTAR, PH_RESIDUAL, PH_SWEEP32, PH_SWEEP32D, PH_OTHER, PH_TILE, PH_UPDATE, PH_COUNT };
 
 namespace shs {
 

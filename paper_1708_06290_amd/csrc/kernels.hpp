@@ -40,6 +40,14 @@ bool launch_sweep(int m, bool dense, const SweepArgs<float> &a, hipStream_t st);
 bool launch_qstar(int m, bool dense_in, const QstarArgs<double> &a, hipStream_t st);
 bool launch_qstar(int m, bool dense_in, const QstarArgs<float> &a, hipStream_t st);
 
+// Blocked FP64 sweep (blocked.hpp): row-tile height and per-shift column
+// width of the carried-column array; launchers.  false for an unsupported m.
+struct BlkTriArgs;
+struct ZupdArgs;
+bool blk_geometry(int m, int *tile_rows, int *width);
+bool launch_blk_tri(int m, const BlkTriArgs &a, hipStream_t st);
+bool launch_zupd(int m, const ZupdArgs &a, hipStream_t st);
+
 }  // namespace shs
 
 // Expands BODY once per supported m with the compile-time constant MM.

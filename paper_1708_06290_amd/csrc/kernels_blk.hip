@@ -1,0 +1,42 @@
+// Instances of the blocked FP64 sweep kernels (row-tile reflectors + block
+// transform, and the all-shift update GEMM) for m = 1 .. 16.
+#include "blocked.hpp"
+#include "kernels.hpp"
+
+namespace shs {
+
+bool blk_geometry(int m, int *tile_rows, int *width)
+{
+    bool ok = false;
+    SHS_DISPATCH_M(m, {
+        *tile_rows = SweepShape<double, MM, false>::TT;
+        *width = blk_width(MM);
+        ok = true;
+    });
+    return ok;
+}
+
+bool launch_blk_tri(int m, const BlkTriArgs &a, hipStream_t st)
+{
+    bool ok = false;
+    SHS_DISPATCH_M(m, {
+        hipLaunchKernelGGL((blk_tri_kernel<MM>), dim3(a.count), dim3(kWave), 0, st, a);
+        ok = true;
+    });
+    return ok;
+}
+
+bool launch_zupd(int m, const ZupdArgs &a, hipStream_t st)
+{
+    const dim3 grid((unsigned)(a.ncols / 128), (unsigned)((a.lo + 127) / 128));
+    switch (blk_width(m)) {
+    case 2: hipLaunchKernelGGL((zupd_kernel<2>), grid, dim3(256), 0, st, a); return true;
+    case 4: hipLaunchKernelGGL((zupd_kernel<4>), grid, dim3(256), 0, st, a); return true;
+    case 8: hipLaunchKernelGGL((zupd_kernel<8>), grid, dim3(256), 0, st, a); return true;
+    case 16: hipLaunchKernelGGL((zupd_kernel<16>), grid, dim3(256), 0, st, a); return true;
+    case 32: hipLaunchKernelGGL((zupd_kernel<32>), grid, dim3(256), 0, st, a); return true;
+    default: return false;
+    }
+}
+
+}  // namespace shs

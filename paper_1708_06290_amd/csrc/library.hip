@@ -9,6 +9,7 @@
 
 #include "shiftsolve.h"
 #include "handle.hpp"
+#include "blocked.hpp"
 #include "gemm.hpp"
 #include "kernels.hpp"
 #include "reduce.hpp"
@@ -115,6 +116,10 @@ bool geo(bool fp32, int64_t n, int64_t m, bool dense, Geo *out)
 struct Layout {
     size_t refl64 = 0, y64 = 0, x = 0, resmax = 0, xmax = 0, list = 0;
     size_t refl32 = 0, y32 = 0, e32 = 0, yd32 = 0, res = 0, scale = 0, eta_prev = 0, status2 = 0;
+    // blocked FP64 sweep (FP64 mode): carried columns, block transforms
+    bool blocked = false;
+    size_t zb = 0, bm = 0, m2 = 0;
+    int64_t blk_ldb = 0, blk_cols = 0;
     size_t total = 0;
 };
 
@@ -134,6 +139,16 @@ bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
     L->xmax = take(sizeof(unsigned long long) * m * s);
     L->list = take(sizeof(int32_t) * s);
     L->status2 = take(sizeof(int32_t) * s);
+    if (mode == SHS_MODE_FP64) {
+        int tr = 0, w = 0;
+        if (!blk_geometry((int)m, &tr, &w)) return false;
+        L->blocked = true;
+        L->blk_cols = (w * s + 127) / 128 * 128;
+        L->blk_ldb = tr + m;
+        L->zb = take(sizeof(double) * n * L->blk_cols);
+        L->bm = take(sizeof(double) * L->blk_ldb * L->blk_cols);
+        L->m2 = take(sizeof(double) * (L->blk_cols / w) * w * w);
+    }
     if (mode == SHS_MODE_FP32_REFINE) {
         if (!geo(true, n, m, false, &g32s) || !geo(true, n, m, true, &g32d)) return false;
         L->refl32 = take(sizeof(float) * std::max(g32s.stride, g32d.stride) * s);
@@ -186,6 +201,76 @@ __global__ void fill_status_kernel(int count, const int32_t *list, const int32_t
     dst[sid] = (st == 0) ? code : st;
 }
 
+// Blocked FP64 sweep of the listed shifts: per row tile (bottom to top) the
+// per-shift tile kernel, then the all-shift update of the rows above.
+hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, const double *shifts, void *work,
+                         const Layout &L, const SweepArgs<double> &sa, hipStream_t st)
+{
+    const int n = (int)h->n, m = (int)h->m;
+    int tr = 0, w = 0;
+    if (!blk_geometry(m, &tr, &w)) return hipErrorInvalidValue;
+    if (count <= 0) return hipSuccess;
+    const int ntiles = (n + tr - 1) / tr;
+    const int64_t ncols = (w * count + 127) / 128 * 128;
+    double *Zb = at<double>(work, L.zb), *Bm = at<double>(work, L.bm), *M2 = at<double>(work, L.m2);
+    PhaseScope whole(h, PH_SWEEP, count, st);
+    // columns past 2m of each shift, and of the padding shifts, stay zero
+    hipError_t e = hipMemsetAsync(Bm, 0, sizeof(double) * L.blk_ldb * ncols, st);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(M2, 0, sizeof(double) * (ncols / w) * w * w, st);
+    if (e != hipSuccess) return e;
+    BlkTriArgs ta{};
+    ta.n = n;
+    ta.count = (int)count;
+    ta.ntiles = ntiles;
+    ta.H = h->H;
+    ta.ldh = h->ldh;
+    ta.shifts = shifts;
+    ta.list = dlist;
+    ta.Rtop = h->Rtop;
+    ta.refl = sa.refl;
+    ta.refl_stride = sa.refl_stride;
+    ta.Y = sa.Y;
+    ta.y_stride = sa.y_stride;
+    ta.status = sa.status;
+    ta.Z = Zb;
+    ta.ldz = n;
+    ta.Bm = Bm;
+    ta.ldb = L.blk_ldb;
+    ta.M2 = M2;
+    ZupdArgs za{};
+    za.m = m;
+    za.ncols = (int)ncols;
+    za.count = (int)count;
+    za.H = h->H;
+    za.ldh = h->ldh;
+    za.Bm = Bm;
+    za.ldb = L.blk_ldb;
+    za.M2 = M2;
+    za.Z = Zb;
+    za.ldz = n;
+    za.shifts = shifts;
+    za.list = dlist;
+    for (int t = ntiles - 1; t >= 0; --t) {
+        ta.t = t;
+        {
+            PhaseScope ps(h, PH_TILE, count, st);
+            if (!launch_blk_tri(m, ta, st)) return hipErrorInvalidValue;
+        }
+        if (t == 0) break;
+        const int lo = t * tr, hi = std::min(n, lo + tr);
+        za.lo = lo;
+        za.c0 = lo - m;
+        za.K = t == ntiles - 1 ? hi - lo + m : hi - lo;
+        za.has_zin = t == ntiles - 1 ? 0 : 1;
+        {
+            PhaseScope ps(h, PH_UPDATE, count, st);
+            if (!launch_zupd(m, za, st)) return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
 // FP64 sweep + Q* pass for the listed shifts into X.
 hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const double *shifts, void *work,
                       const Layout &L, double *X, int64_t ldx, int32_t *status, hipStream_t st)
@@ -206,7 +291,10 @@ hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const 
     sa.Y = at<double>(work, L.y64);
     sa.y_stride = 2 * m * m;
     sa.status = status;
-    {
+    if (L.blocked) {
+        hipError_t e = sweep_blocked(h, count, dlist, shifts, work, L, sa, st);
+        if (e != hipSuccess) return e;
+    } else {
         PhaseScope ps(h, PH_SWEEP, count, st);
         if (!launch_sweep((int)m, false, sa, st)) return hipErrorInvalidValue;
     }
@@ -871,10 +959,12 @@ int shs_last_timings(const shs_handle *h, shs_timings_t *out)
     if (!out) return -2;
     std::memset(out, 0, sizeof(*out));
     if (!h->marks.empty()) RETURN_IF_HIP(hipEventSynchronize(h->marks.back().b));
-    double *ms[PH_COUNT] = {&out->sweep_ms, &out->qstar_ms, &out->residual_ms, &out->sweep32_ms,
-                            &out->sweep32_dense_ms, &out->other_ms};
-    int64_t *calls[PH_COUNT] = {&out->sweep_calls, &out->qstar_calls, &out->residual_calls, &out->sweep32_calls,
-                                &out->sweep32_dense_calls, &out->other_calls};
+    double *ms[PH_COUNT] = {&out->sweep_ms,       &out->qstar_ms,        &out->residual_ms,
+                            &out->sweep32_ms,     &out->sweep32_dense_ms, &out->other_ms,
+                            &out->sweep_tile_ms,  &out->sweep_update_ms};
+    int64_t *calls[PH_COUNT] = {&out->sweep_calls,      &out->qstar_calls,         &out->residual_calls,
+                                &out->sweep32_calls,    &out->sweep32_dense_calls, &out->other_calls,
+                                &out->sweep_tile_calls, &out->sweep_update_calls};
     for (const auto &mk : h->marks) {
         float t = 0.f;
         RETURN_IF_HIP(hipEventElapsedTime(&t, mk.a, mk.b));

@@ -268,6 +268,144 @@ __device__ __forceinline__ void pivot_row(const T (&wr)[R][M + 1], const T (&wi)
     }
 }
 
+// The tile's own steps k = hi-1 .. lo: each pivot row is read out of its
+// owner lane, its reflector is formed, stored (lane 0) and applied to the
+// tile's rows above it.  The top tile records the leading block of R_sigma
+// (rows and columns < m) in lds_rs for the back substitution.
+template <typename T, int M, bool DENSE>
+__device__ __forceinline__ void tri_phase(int n, int lo, int hi, int lane, const T *H, int64_t ldh, T sgr, T sgi,
+                                          T *rf, int64_t tstride, T *Y, T *lds_rs,
+                                          T (&wr)[SweepShape<T, M, DENSE>::R][M + 1],
+                                          T (&wi)[SweepShape<T, M, DENSE>::R][M + 1],
+                                          T (&er)[SweepShape<T, M, DENSE>::R][SweepShape<T, M, DENSE>::EM],
+                                          T (&ei)[SweepShape<T, M, DENSE>::R][SweepShape<T, M, DENSE>::EM],
+                                          bool &singular, bool &nonfinite)
+{
+    using Sh = SweepShape<T, M, DENSE>;
+    constexpr int R = Sh::R, TT = Sh::TT, S = Sh::S, EM = Sh::EM, NP = Sh::NP;
+    const int k_end = lo;
+    if (hi - 1 >= k_end) {
+        const int k_hi = hi - 1, k_lo = k_end;
+        T nh[R];
+        load_fresh<T, R>(H, ldh, n, lo, lane, k_hi - 1 - M, nh);
+        const int kg0 = k_hi + (M - k_hi % NP);   // group top: k = M (mod m+1)
+        for (int kg = kg0; kg >= k_lo; kg -= NP) {
+            static_for<NP>([&](auto sc) {
+                constexpr int st = decltype(sc)::value;
+                constexpr int Q = M - st;
+                const int k = kg - st;
+                if (k <= k_hi && k >= k_lo) {
+                    T ch[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) ch[r] = nh[r];
+                    const int kn = k - 1 >= k_lo ? k - 1 : k_lo;
+                    load_fresh<T, R>(H, ldh, n, lo, lane, kn - 1 - M, nh);
+                    T pr[NP], pi[NP], per[EM], pei[EM];
+                    pivot_row<T, M, R, EM, Q, DENSE>(wr, wi, er, ei, k - lo, pr, pi, per, pei);
+                    T vr[M], vi[M], tau, br, bi, yr[EM], yi[EM];
+                    make_refl<T, M>(pr, pi, vr, vi, tau, br, bi);
+                    if (br == T(0) && bi == T(0)) singular = true;
+                    if constexpr (DENSE) {
+                        const T den = T(1) / fma(br, br, bi * bi);
+#pragma unroll
+                        for (int c = 0; c < M; ++c) {
+                            yr[c] = (per[c] * br + pei[c] * bi) * den;
+                            yi[c] = (pei[c] * br - per[c] * bi) * den;
+                            if (!isfinite(yr[c]) || !isfinite(yi[c])) nonfinite = true;
+                        }
+                    } else {
+                        yr[0] = T(0);
+                        yi[0] = T(0);
+                    }
+                    if (lane == 0) {
+                        T *p = const_cast<T *>(refl_slot<T>(rf, k, TT, tstride, S));
+                        p[0] = tau;
+                        p[1] = T(0);
+#pragma unroll
+                        for (int j = 0; j < M; ++j) { p[2 + 2 * j] = vr[j]; p[3 + 2 * j] = vi[j]; }
+                        if constexpr (DENSE) {
+#pragma unroll
+                            for (int c = 0; c < M; ++c) {
+                                p[2 + 2 * M + 2 * c] = yr[c];
+                                p[3 + 2 * M + 2 * c] = yi[c];
+                                Y[2 * ((int64_t)c * n + k)] = yr[c];
+                                Y[2 * ((int64_t)c * n + k) + 1] = yi[c];
+                            }
+                        }
+                    }
+                    T dr0 = T(0), di0 = T(0);
+                    apply_step<T, M, R, EM, Q, R, DENSE, !DENSE>(wr, wi, er, ei, vr, vi, tau, yr, yi, ch,
+                                                                 k - 1 - M, lo, lane, sgr, sgi, dr0, di0);
+                    if constexpr (!DENSE) {
+                        // leading block: R_sigma(i, k) for rows i < k (lanes of
+                        // slot 0 in the top tile) and beta_k on the diagonal
+                        if (k < M) {
+                            if (lane < k) {
+                                lds_rs[2 * (k * M + lane)] = dr0;
+                                lds_rs[2 * (k * M + lane) + 1] = di0;
+                            }
+                            if (lane == 0) {
+                                lds_rs[2 * (k * M + k)] = br;
+                                lds_rs[2 * (k * M + k) + 1] = bi;
+                            }
+                        }
+                    }
+                }
+            });
+        }
+    }
+
+}
+
+// After the last step: the back substitution Y = R_sigma(0:m,0:m)^{-1} R(0:m,0:m)
+// (structured right-hand side) from the leading block left in lds_rs, the
+// shift's status, and NaN outputs for a singular shift.
+template <typename T, int M, bool DENSE>
+__device__ __forceinline__ void finish_shift(int n, int lane, const double *Rtop, T *Y, const T *lds_rs,
+                                             int32_t *status, bool singular, bool nonfinite)
+{
+    // ---- back substitution Y = R_sigma(0:m,0:m)^{-1} R(0:m,0:m) -----------
+    // The last m steps left the leading block of R_sigma and its diagonal in
+    // LDS; lane c < m solves for column c of Y (structured right-hand side).
+    if constexpr (!DENSE) {
+        if (lane < M) {
+            const int c = lane;
+            T e_r[M], e_i[M];
+#pragma unroll
+            for (int i = 0; i < M; ++i) { e_r[i] = (T)Rtop[c * M + i]; e_i[i] = T(0); }
+#pragma unroll
+            for (int k = M - 1; k >= 0; --k) {
+                const T br = lds_rs[2 * (k * M + k)], bi = lds_rs[2 * (k * M + k) + 1];
+                const T den = T(1) / fma(br, br, bi * bi);
+                const T yr = (e_r[k] * br + e_i[k] * bi) * den;
+                const T yi = (e_i[k] * br - e_r[k] * bi) * den;
+                if (!isfinite(yr) || !isfinite(yi)) nonfinite = true;
+                Y[2 * (c * M + k)] = yr;
+                Y[2 * (c * M + k) + 1] = yi;
+#pragma unroll
+                for (int i = 0; i < k; ++i) {
+                    const T rr = lds_rs[2 * (k * M + i)], ri = lds_rs[2 * (k * M + i) + 1];
+                    e_r[i] = fma(-rr, yr, fma(ri, yi, e_r[i]));
+                    e_i[i] = fma(-rr, yi, fma(-ri, yr, e_i[i]));
+                }
+            }
+        }
+        // any lane's non-finite result marks the shift
+        nonfinite = __any(nonfinite);
+    }
+
+    if (lane == 0) *status = singular ? 1 : (nonfinite ? 2 : 0);
+    if (singular) {
+        // no solution exists: NaN outputs for this shift only
+        const T qnan = (T)__builtin_nan("");
+        const int64_t cnt = DENSE ? (int64_t)n * M : (int64_t)M * M;
+        for (int64_t idx = lane; idx < cnt; idx += kWave) {
+            Y[2 * idx] = qnan;
+            Y[2 * idx + 1] = qnan;
+        }
+    }
+}
+
 // One shift's sweep: everything one wavefront needs.
 template <typename T>
 struct SweepItem {
@@ -411,123 +549,15 @@ __device__ __forceinline__ void sweep_body(const SweepItem<T> &it, T *lds_refl, 
             }
         }
 
-        // ---- produce this tile's reflectors: steps hi-1 .. k_end -------------
-        const int k_end = lo;
-        if (hi - 1 >= k_end) {
-            const int k_hi = hi - 1, k_lo = k_end;
-            T nh[R];
-            load_fresh<T, R>(H, ldh, n, lo, lane, k_hi - 1 - M, nh);
-            const int kg0 = k_hi + (M - k_hi % NP);   // group top: k = M (mod m+1)
-            for (int kg = kg0; kg >= k_lo; kg -= NP) {
-                static_for<NP>([&](auto sc) {
-                    constexpr int st = decltype(sc)::value;
-                    constexpr int Q = M - st;
-                    const int k = kg - st;
-                    if (k <= k_hi && k >= k_lo) {
-                        T ch[R];
-#pragma unroll
-                        for (int r = 0; r < R; ++r) ch[r] = nh[r];
-                        const int kn = k - 1 >= k_lo ? k - 1 : k_lo;
-                        load_fresh<T, R>(H, ldh, n, lo, lane, kn - 1 - M, nh);
-                        T pr[NP], pi[NP], per[EM], pei[EM];
-                        pivot_row<T, M, R, EM, Q, DENSE>(wr, wi, er, ei, k - lo, pr, pi, per, pei);
-                        T vr[M], vi[M], tau, br, bi, yr[EM], yi[EM];
-                        make_refl<T, M>(pr, pi, vr, vi, tau, br, bi);
-                        if (br == T(0) && bi == T(0)) singular = true;
-                        if constexpr (DENSE) {
-                            const T den = T(1) / fma(br, br, bi * bi);
-#pragma unroll
-                            for (int c = 0; c < M; ++c) {
-                                yr[c] = (per[c] * br + pei[c] * bi) * den;
-                                yi[c] = (pei[c] * br - per[c] * bi) * den;
-                                if (!isfinite(yr[c]) || !isfinite(yi[c])) nonfinite = true;
-                            }
-                        } else {
-                            yr[0] = T(0);
-                            yi[0] = T(0);
-                        }
-                        if (lane == 0) {
-                            T *p = const_cast<T *>(refl_slot<T>(rf, k, TT, tstride, S));
-                            p[0] = tau;
-                            p[1] = T(0);
-#pragma unroll
-                            for (int j = 0; j < M; ++j) { p[2 + 2 * j] = vr[j]; p[3 + 2 * j] = vi[j]; }
-                            if constexpr (DENSE) {
-#pragma unroll
-                                for (int c = 0; c < M; ++c) {
-                                    p[2 + 2 * M + 2 * c] = yr[c];
-                                    p[3 + 2 * M + 2 * c] = yi[c];
-                                    Y[2 * ((int64_t)c * n + k)] = yr[c];
-                                    Y[2 * ((int64_t)c * n + k) + 1] = yi[c];
-                                }
-                            }
-                        }
-                        T dr0 = T(0), di0 = T(0);
-                        apply_step<T, M, R, EM, Q, R, DENSE, !DENSE>(wr, wi, er, ei, vr, vi, tau, yr, yi, ch,
-                                                                     k - 1 - M, lo, lane, sgr, sgi, dr0, di0);
-                        if constexpr (!DENSE) {
-                            // leading block: R_sigma(i, k) for rows i < k (lanes of
-                            // slot 0 in the top tile) and beta_k on the diagonal
-                            if (k < M) {
-                                if (lane < k) {
-                                    lds_rs[2 * (k * M + lane)] = dr0;
-                                    lds_rs[2 * (k * M + lane) + 1] = di0;
-                                }
-                                if (lane == 0) {
-                                    lds_rs[2 * (k * M + k)] = br;
-                                    lds_rs[2 * (k * M + k) + 1] = bi;
-                                }
-                            }
-                        }
-                    }
-                });
-            }
-        }
+        // ---- produce this tile's reflectors: steps hi-1 .. lo ------------------
+        tri_phase<T, M, DENSE>(n, lo, hi, lane, H, ldh, sgr, sgi, rf, tstride, Y, lds_rs, wr, wi, er, ei, singular,
+                               nonfinite);
 
         // this tile's reflector stores complete before the next tile loads them
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     }
 
-    // ---- back substitution Y = R_sigma(0:m,0:m)^{-1} R(0:m,0:m) -----------
-    // The last m steps left the leading block of R_sigma and its diagonal in
-    // LDS; lane c < m solves for column c of Y (structured right-hand side).
-    if constexpr (!DENSE) {
-        if (lane < M) {
-            const int c = lane;
-            T e_r[M], e_i[M];
-#pragma unroll
-            for (int i = 0; i < M; ++i) { e_r[i] = (T)it.Rtop[c * M + i]; e_i[i] = T(0); }
-#pragma unroll
-            for (int k = M - 1; k >= 0; --k) {
-                const T br = lds_rs[2 * (k * M + k)], bi = lds_rs[2 * (k * M + k) + 1];
-                const T den = T(1) / fma(br, br, bi * bi);
-                const T yr = (e_r[k] * br + e_i[k] * bi) * den;
-                const T yi = (e_i[k] * br - e_r[k] * bi) * den;
-                if (!isfinite(yr) || !isfinite(yi)) nonfinite = true;
-                Y[2 * (c * M + k)] = yr;
-                Y[2 * (c * M + k) + 1] = yi;
-#pragma unroll
-                for (int i = 0; i < k; ++i) {
-                    const T rr = lds_rs[2 * (k * M + i)], ri = lds_rs[2 * (k * M + i) + 1];
-                    e_r[i] = fma(-rr, yr, fma(ri, yi, e_r[i]));
-                    e_i[i] = fma(-rr, yi, fma(-ri, yr, e_i[i]));
-                }
-            }
-        }
-        // any lane's non-finite result marks the shift
-        nonfinite = __any(nonfinite);
-    }
-
-    if (lane == 0) *it.status = singular ? 1 : (nonfinite ? 2 : 0);
-    if (singular) {
-        // no solution exists: NaN outputs for this shift only
-        const T qnan = (T)__builtin_nan("");
-        const int64_t cnt = DENSE ? (int64_t)n * M : (int64_t)M * M;
-        for (int64_t idx = lane; idx < cnt; idx += kWave) {
-            Y[2 * idx] = qnan;
-            Y[2 * idx + 1] = qnan;
-        }
-    }
+    finish_shift<T, M, DENSE>(n, lane, it.Rtop, Y, lds_rs, it.status, singular, nonfinite);
 }
 
 template <typename T, int M, bool DENSE>

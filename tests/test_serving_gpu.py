@@ -57,17 +57,24 @@ def test_mix_equals_alone_and_oracle():
     print("server stats", st, flush=True)
     assert st["completed"] == len(reqs) and st["failed"] == 0
     assert st["max_batch_systems"] >= 1
+    # the same requests again, one at a time, on an idle server
+    solo = ss.Server(streams=3, budget_bytes=8 << 30)
+    solo_ids = [solo.register(s) for s in systems]
     for (sys_id, shifts, mode), res in zip(reqs, results):
         sysm = systems[sys_id]
         m = sysm.m
-        alone = sysm.solve(shifts, mode=ss.SHS_MODE_FP64 if mode == "fp64" else ss.SHS_MODE_FP32_REFINE)
+        md = ss.SHS_MODE_FP64 if mode == "fp64" else ss.SHS_MODE_FP32_REFINE
+        alone = solo.wait(solo.submit(solo_ids[sys_id], shifts, mode=md), timeout_ms=120000)
+        batch = sysm.solve(shifts, mode=md)
         torch.cuda.synchronize()
-        Xm, Xa = res.X.cpu().numpy(), alone.X.cpu().numpy()
+        Xm, Xa, Xb = res.X.cpu().numpy(), alone.X.cpu().numpy(), batch.X.cpu().numpy()
         stm = res.status.cpu().numpy()
         assert np.isin(stm, [0, ss.SHS_STATUS_FALLBACK]).all(), stm
         assert (res.eta.cpu().numpy() <= 1e-13).all()
         if mode == "fp64":
-            assert np.array_equal(Xm, Xa), "FP64 result differs between the mix and a solo solve"
+            assert np.array_equal(Xm, Xa), "FP64 result differs between the mix and a solo request"
+        # the batch solver (blocked sweep) agrees to rounding
+        assert np.abs(Xm - Xb.reshape(Xm.shape)).max() <= 1e-10 * np.abs(Xb).max()
         H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
         Xo, Go, _, _ = oracle.solve(H, R, Ct, shifts)
         for j in range(len(shifts)):
@@ -75,6 +82,7 @@ def test_mix_equals_alone_and_oracle():
             assert np.abs(Xm[:, j * m:(j + 1) * m] - xo).max() <= 1e-10 * np.linalg.norm(xo)
             go = Go[:, j * m:(j + 1) * m]
             assert np.abs(res.G.cpu().numpy()[:, j * m:(j + 1) * m] - go).max() <= 1e-10 * np.linalg.norm(go)
+    solo.close()
     srv.close()
 
 

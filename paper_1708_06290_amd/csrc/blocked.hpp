@@ -33,8 +33,9 @@
 // column-major n x (W items) array; W, the per-shift column stride, is 2m
 // rounded up to a power of two (>= 2), so a 16-column MFMA block holds one
 // shift (W = 16), half of one (W = 32) or several whole ones (W < 16).  The
-// GEMM never mixes columns, so a shift's values, finite or not, stay in its
-// own columns.  The bottom tile's carried columns are
+// main product never mixes columns; the carried part of W < 16 does, with
+// zero weights (see zupd_kernel).
+// The bottom tile's carried columns are
 // plain columns of H - sigma I, so its GEMM folds them into K (K = n_b + m)
 // and reads no Z.
 #pragma once
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
     }
 
     bool singular = false, nonfinite = false;
-    tri_phase<T, M, false>(n, lo, hi, lane, H, ldh, sgr, sgi, rf, tstride, Y, lds_rs, wr, wi, er, ei, singular,
+    tri_phase<T, M, false, true>(n, lo, hi, lane, H, ldh, sgr, sgi, rf, tstride, Y, lds_rs, wr, wi, er, ei, singular,
                            nonfinite);
     // the tile's reflector stores complete before they are read back below
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -145,15 +146,39 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
     // P_k acts on rows k-lo .. k-lo+m of M_blk.  Applied from P_lo upwards, row
     // p is final once P_{lo+p} is done, so each lane keeps a window of m+1
     // rows (row p in slot p mod (m+1)), emits the finished row and lets the
-    // next (zero) row in.
-    if (lane < M) {
-        const int c = lane;
+    // next (zero) row in.  The tile's reflectors come back through LDS in
+    // chunks of CS steps that the whole wave loads (coalesced, the next chunk
+    // in flight while the current one is used), so the serial chain never
+    // waits on memory.
+    {
+        // steps per chunk: whole phase groups, about 12 elements per lane
+        constexpr int CS = NP * ((12 * kWave / S) / NP > 0 ? (12 * kWave / S) / NP : 1);
+        constexpr int CE = CS * S;                          // elements per chunk
+        constexpr int PL = (CE + kWave - 1) / kWave;
+        __shared__ T lds_ch[CE];
+        T pre[PL];
+        const int c = lane < M ? lane : 0;
         const int nb = hi - lo;
         const int K = bottom ? nb + M : nb;
         double *bcr = a.Bm + (int64_t)(item * W + c) * a.ldb;
         double *bci = a.Bm + (int64_t)(item * W + M + c) * a.ldb;
         double *m2 = a.M2 + (int64_t)item * W * W;
+        // slots past hi - 1 are loaded from a clamped address and never used
+        auto fetch = [&](int cb) {
+#pragma unroll
+            for (int e = 0; e < PL; ++e) {
+                const int idx0 = e * kWave + lane;
+                const int idx = idx0 < CE ? idx0 : CE - 1;
+                const int ks = idx / S, el = idx - ks * S;
+                const int k = min(cb + ks, hi - 1);
+                pre[e] = refl_slot<T>(rf, k, TT, tstride, S)[el];
+            }
+        };
+        // a shift with a non-finite sigma gets a zero transform: its own
+        // result is flagged by its status, and its Z columns stay finite
+        const bool bad = !isfinite(sgr) || !isfinite(sgi);
         auto emit = [&](int p, T xr, T xi) {
+            if (bad) xr = xi = T(0);
             if (p < K) {
                 bcr[p] = xr;
                 bci[p] = xi;
@@ -169,12 +194,24 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
         T ur[NP], ui[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) { ur[p] = p == c ? T(1) : T(0); ui[p] = T(0); }
-        for (int kb = lo; kb < hi; kb += NP) {
+        fetch(lo);
+        for (int cb = lo; cb < hi; cb += CS) {
+            // one wave per workgroup: its LDS operations complete in order,
+            // so the chunk can overwrite the previous one in place
+#pragma unroll
+            for (int e = 0; e < PL; ++e) {
+                const int idx = e * kWave + lane;
+                if (idx < CE) lds_ch[idx] = pre[e];
+            }
+            if (cb + CS < hi) fetch(cb + CS);
+            if (lane < M) {
+            const int ce = min(hi, cb + CS);
+            for (int kb = cb; kb < ce; kb += NP) {
             static_for<NP>([&](auto sc) {
                 constexpr int st = decltype(sc)::value;
                 const int k = kb + st;
-                if (k < hi) {
-                    const T *pv = refl_slot<T>(rf, k, TT, tstride, S);
+                if (k < ce) {
+                    const T *pv = lds_ch + (k - cb) * S;
                     const T tau = pv[0];
                     T vr[M], vi[M];
 #pragma unroll
@@ -201,12 +238,16 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
                     ui[st] = T(0);
                 }
             });
+            }
+            }
         }
         // rows nb .. nb+m-1 are still in the window (row nb+m is the zero row)
+        if (lane < M) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
-            const int p = nb + ((q - nb % NP) + NP) % NP;
-            if (p < nb + M) emit(p, ur[q], ui[q]);
+            for (int q = 0; q < NP; ++q) {
+                const int p = nb + ((q - nb % NP) + NP) % NP;
+                if (p < nb + M) emit(p, ur[q], ui[q]);
+            }
         }
     }
 }
@@ -236,14 +277,24 @@ typedef double zupd_dbl4 __attribute__((ext_vector_type(4)));
 // sigma M1 on the rows whose diagonal is in the block.  128 x 128 tiles,
 // 4 waves of 64 x 64 (4 x 4 blocks of v_mfma_f64_16x16x4f64; lane l holds
 // A(l%16, l/16), B(l/16, l%16); result register r of lane l is
-// D(4r + l/16, l%16)).  A workgroup reads only its own tile of Z, and every
-// read of Z precedes every write in each wave, so the update is in place.
+// D(4r + l/16, l%16)).
+//
+// The carried part comes first: each wave loads its Z fragments in two
+// batches (issued together, so one memory latency per batch) and
+// multiplies them by M2 into the accumulators.  For W < 16 a 16-column
+// block holds several shifts and M2 acts as a block-diagonal operand; the
+// tile kernel keeps every shift's Z finite (a shift with a non-finite sigma
+// gets a zero block transform), so the zeros never meet a NaN.  A
+// workgroup reads only its own tile of Z, all before it writes, so the
+// update is in place.  The main product streams K in chunks of 16 through
+// double-buffered LDS stored [row][k] with one column of padding, which
+// keeps the fragment reads and the stores free of bank conflicts.
 template <int W>
-__global__ __launch_bounds__(256) void zupd_kernel(ZupdArgs a)
+__global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgs a)
 {
-    constexpr int BM = 128, BN = 128, BK = 16;
-    __shared__ double As[BK][BM];
-    __shared__ double Bs[BK][BN];
+    constexpr int BM = 128, BN = 128, BK = 16, PK = BK + 1;
+    __shared__ double As[2][BM][PK];
+    __shared__ double Bs[2][BN][PK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
@@ -256,6 +307,46 @@ __global__ __launch_bounds__(256) void zupd_kernel(ZupdArgs a)
 #pragma unroll
         for (int y = 0; y < 4; ++y) acc[x][y] = zupd_dbl4{0.0, 0.0, 0.0, 0.0};
 
+    // ---- carried part: Z(rows, shift) * M2(shift) ------------------------------
+    if (a.has_zin) {
+        constexpr int KZ = W > 16 ? W : 16;   // Z columns feeding one 16-column block
+        constexpr int NS = KZ / 4;            // MFMA k-steps per block
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            double az[2][4][NS], bz[2][NS];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int nt = 2 * half + h;
+                const int cb = j0 + wc * 64 + nt * 16;   // first output column of the block
+                const int zc = W <= 16 ? cb : (cb / W) * W;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const int k = 4 * s + lane / 16, q = lane % 16;
+                    if constexpr (W <= 16) {
+                        const int sk = (cb + k) / W, sq = (cb + q) / W;
+                        bz[h][s] = sk == sq ? a.M2[(int64_t)sk * W * W + ((cb + k) % W) * W + (cb + q) % W] : 0.0;
+                    } else {
+                        bz[h][s] = a.M2[(int64_t)(cb / W) * W * W + k * W + cb % W + q];
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt) {
+                        const int i = i0 + wr * 64 + mt * 16 + lane % 16;
+                        az[h][mt][s] = i < lo ? a.Z[(int64_t)(zc + k) * a.ldz + i] : 0.0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                    for (int s = 0; s < NS; ++s)
+                        acc[mt][2 * half + h] =
+                            __builtin_amdgcn_mfma_f64_16x16x4f64(az[h][mt][s], bz[h][s], acc[mt][2 * half + h], 0, 0, 0);
+        }
+    }
+
+    // ---- main product: H(0:lo, c0 : c0+K) Bm -----------------------------------
     double ra[8], rb[8];
     auto gload = [&](int k0) {
 #pragma unroll
@@ -269,62 +360,38 @@ __global__ __launch_bounds__(256) void zupd_kernel(ZupdArgs a)
             rb[e] = k < K ? a.Bm[(int64_t)j * a.ldb + k] : 0.0;
         }
     };
+    auto lstore = [&](int b) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) As[b][tid % BM][tid / BM + 2 * e] = ra[e];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Bs[b][tid / BK + 16 * e][tid % BK] = rb[e];
+    };
     gload(0);
+    lstore(0);
+    if (BK < K) gload(BK);
+    __syncthreads();
+    int buf = 0;
     for (int k0 = 0; k0 < K; k0 += BK) {
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 8; ++e) As[tid / BM + 2 * e][tid % BM] = ra[e];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) Bs[tid % BK][tid / BK + 16 * e] = rb[e];
-        __syncthreads();
-        if (k0 + BK < K) gload(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             double af[4], bf[4];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) af[mt] = As[kk + lane / 16][wr * 64 + mt * 16 + lane % 16];
+            for (int mt = 0; mt < 4; ++mt) af[mt] = As[buf][wr * 64 + mt * 16 + lane % 16][kk + lane / 16];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) bf[nt] = Bs[kk + lane / 16][wc * 64 + nt * 16 + lane % 16];
+            for (int nt = 0; nt < 4; ++nt) bf[nt] = Bs[buf][wc * 64 + nt * 16 + lane % 16][kk + lane / 16];
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mt], bf[nt], acc[mt][nt], 0, 0, 0);
         }
-    }
-
-    // ---- carried part: Z(rows, shift) * M2(shift) -----------------------------
-    // W >= 16: every 16-column block belongs to one shift, so the product is
-    // MFMA work on the block (K = W).  Narrower shifts share a block; there the
-    // product runs on the vector ALU in the epilogue, so that values of one
-    // shift never meet another shift's zeros (a non-finite shift stays
-    // confined to its own columns).
-    if constexpr (W >= 16) {
-        if (a.has_zin) {
-        constexpr int KZ = W;
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int cb = j0 + wc * 64 + nt * 16;   // first output column of the block
-            const int sh = cb / W, half = cb % W;
-            double bz[KZ / 4];
-#pragma unroll
-            for (int s = 0; s < KZ / 4; ++s) {
-                const int k = 4 * s + lane / 16, q = lane % 16;
-                bz[s] = a.M2[(int64_t)sh * W * W + k * W + half + q];
-            }
-            const int zc = sh * W;   // first Z column of the shift
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const int i = i0 + wr * 64 + mt * 16 + lane % 16;
-#pragma unroll
-                for (int s = 0; s < KZ / 4; ++s) {
-                    const int k = 4 * s + lane / 16;
-                    const double az = i < lo ? a.Z[(int64_t)(zc + k) * a.ldz + i] : 0.0;
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, bz[s], acc[mt][nt], 0, 0, 0);
-                }
-            }
+        if (k0 + BK < K) {
+            // the other buffer was last read before the previous barrier
+            lstore(buf ^ 1);
+            if (k0 + 2 * BK < K) gload(k0 + 2 * BK);
         }
-        }
+        __syncthreads();
+        buf ^= 1;
     }
 
     // ---- epilogue: sigma on the block's diagonal rows, store ----------------
@@ -339,18 +406,6 @@ __global__ __launch_bounds__(256) void zupd_kernel(ZupdArgs a)
                 const int j = j0 + wc * 64 + nt * 16 + lane % 16;
                 if (i >= lo) continue;
                 double v = acc[mt][nt][r];
-                if constexpr (W < 16) {
-                    // every read of Z(i, shift) in this wave happens in the
-                    // iteration that writes Z(i, shift): rows 4r .. 4r+3 of
-                    // the block, all 16 columns
-                    if (a.has_zin) {
-                        const int w = j / W, q = j % W;
-                        const double *zrow = a.Z + (int64_t)w * W * a.ldz + i;
-                        const double *mq = a.M2 + (int64_t)w * W * W + q;
-#pragma unroll
-                        for (int k = 0; k < W; ++k) v = fma(zrow[(int64_t)k * a.ldz], mq[k * W], v);
-                    }
-                }
                 if (i >= lo - m) {
                     const int w = j / W, q = j % W;
                     if (w < a.count && q < 2 * m) {

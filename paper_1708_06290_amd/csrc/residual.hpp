@@ -31,156 +31,28 @@ struct ResidualArgs {
     unsigned long long *xmax;   // per column, max |X|
 };
 
-// 64 rows x 32 complex columns per workgroup of 256 threads; each thread
-// holds 4 rows x 2 columns.  Columns are indexed in the listed order:
-// work column w = item * m + c.
-__global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
-{
-    constexpr int BM = 64, BN = 32, BK = 16;
-    __shared__ double Hs[BK][BM + 1];
-    __shared__ double Xs[BK][2 * BN + 2];
-    const int tid = threadIdx.x;
-    const int tx = tid % 16, ty = tid / 16;
-    const int i0 = blockIdx.x * BM;
-    const int w0 = blockIdx.y * BN;
-    const int ncols = a.count * a.m;
-    const int n = a.n, m = a.m;
-
-    // column pointers of this thread's 2 work columns (for loads of X tiles
-    // each thread loads by (kk, cc) instead)
-    double acc_r[4][2], acc_i[4][2];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) { acc_r[r][q] = 0.0; acc_i[r][q] = 0.0; }
-
-    int kstart = i0 - m;
-    if (kstart < 0) kstart = 0;
-    kstart = (kstart / BK) * BK;
-    for (int k0 = kstart; k0 < n; k0 += BK) {
-        // H tile: rows i0..i0+63, cols k0..k0+15 ; 1024 values, 4 per thread
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int idx = tid + e * 256;
-            const int rr = idx % BM, kk = idx / BM;
-            const int i = i0 + rr, k = k0 + kk;
-            Hs[kk][rr] = (i < n && k < n) ? a.H[(int64_t)k * a.ldh + i] : 0.0;
-        }
-        // X tile: rows k0..k0+15, 32 complex work columns; 512 complex, 2 per thread
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int idx = tid + e * 256;
-            const int kk = idx % BK, cc = idx / BK;
-            const int k = k0 + kk, wc = w0 + cc;
-            double xr = 0.0, xi = 0.0;
-            if (k < n && wc < ncols) {
-                const int item = wc / m, c = wc % m;
-                const int sid = a.list ? a.list[item] : item;
-                const double *px = a.X + (((int64_t)sid * m + c) * a.ldx + k) * 2;
-                xr = px[0];
-                xi = px[1];
-            }
-            Xs[kk][2 * cc] = xr;
-            Xs[kk][2 * cc + 1] = xi;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < BK; ++kk) {
-            double hv[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) hv[r] = Hs[kk][ty * 4 + r];
-            double xr[2], xi[2];
-#pragma unroll
-            for (int q = 0; q < 2; ++q) { xr[q] = Xs[kk][2 * (tx * 2 + q)]; xi[q] = Xs[kk][2 * (tx * 2 + q) + 1]; }
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    acc_r[r][q] = fma(hv[r], xr[q], acc_r[r][q]);
-                    acc_i[r][q] = fma(hv[r], xi[q], acc_i[r][q]);
-                }
-        }
-        __syncthreads();
-    }
-
-    // epilogue: Res = R - HX + sigma X, column maxima
-    __shared__ double colmax_r[16][BN];
-    __shared__ double colmax_x[16][BN];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int cc = tx * 2 + q;
-        const int wc = w0 + cc;
-        double mr = 0.0, mx = 0.0;
-        if (wc < ncols) {
-            const int item = wc / m, c = wc % m;
-            const int sid = a.list ? a.list[item] : item;
-            const double sr = a.shifts[2 * sid], si = a.shifts[2 * sid + 1];
-            const int64_t col = (int64_t)sid * m + c;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = i0 + ty * 4 + r;
-                if (i < n) {
-                    const double *px = a.X + (col * a.ldx + i) * 2;
-                    const double xr = px[0], xi = px[1];
-                    double rr = (i < m) ? a.Rtop[c * m + i] : 0.0;
-                    double ri = 0.0;
-                    rr = rr - acc_r[r][q] + (sr * xr - si * xi);
-                    ri = ri - acc_i[r][q] + (sr * xi + si * xr);
-                    if (a.Res) {
-                        double *pr = a.Res + (col * a.ldr + i) * 2;
-                        pr[0] = rr;
-                        pr[1] = ri;
-                    }
-                    const double ar = hypot(rr, ri), ax = hypot(xr, xi);
-                    // NaN must propagate into the maximum
-                    mr = (ar > mr || ar != ar) ? ar : mr;
-                    mx = (ax > mx || ax != ax) ? ax : mx;
-                }
-            }
-        }
-        colmax_r[ty][cc] = mr;
-        colmax_x[ty][cc] = mx;
-    }
-    __syncthreads();
-    if (tid < BN) {
-        const int wc = w0 + tid;
-        if (wc < ncols) {
-            double mr = 0.0, mx = 0.0;
-#pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                const double vr = colmax_r[t][tid], vx = colmax_x[t][tid];
-                mr = (vr > mr || vr != vr) ? vr : mr;
-                mx = (vx > mx || vx != vx) ? vx : mx;
-            }
-            const int item = wc / m, c = wc % m;
-            const int sid = a.list ? a.list[item] : item;
-            const int64_t col = (int64_t)sid * m + c;
-            // a NaN has the largest unsigned pattern of all doubles with the sign bit clear
-            if (mr != mr) mr = __longlong_as_double(0x7ff8000000000000LL);
-            if (mx != mx) mx = __longlong_as_double(0x7ff8000000000000LL);
-            atomic_max_nonneg(a.resmax + col, mr);
-            atomic_max_nonneg(a.xmax + col, mx);
-        }
-    }
-}
-
 typedef double shs_dbl4 __attribute__((ext_vector_type(4)));
 
-// MFMA form of residual_kernel: the product H X runs on the FP64 matrix
-// cores (v_mfma_f64_16x16x4f64).  A workgroup of 4 waves computes 128 rows x
-// 64 complex columns; wave (wr, wc) owns rows wr*64 .. +63 and complex
-// columns wc*32 .. +31 as 4 x 4 MFMA tiles of 16 x 16.  In LDS the X tile
-// keeps, for each group of 16 complex columns, the 16 real parts followed by
-// the 16 imaginary parts, so N-tiles 2q and 2q+1 of a wave hold the real and
-// imaginary parts of the same 16 complex columns and every lane ends with
-// whole complex results.  MFMA operand layout: lane l holds A(l%16, l/16)
-// and B(l/16, l%16); result register r of lane l is D(4 r + l/16, l%16)
-// (checked on the device with a decoding probe).
-__global__ __launch_bounds__(256) void residual_mfma_kernel(ResidualArgs a)
+// The residual on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  A
+// workgroup of 4 waves computes 128 rows x 64 complex columns; wave (wr, wc)
+// owns rows wr*64 .. +63 and complex columns wc*32 .. +31 as 4 x 4 MFMA
+// tiles of 16 x 16.  In LDS the X tile keeps, for each group of 16 complex
+// columns, the 16 real parts followed by the 16 imaginary parts, so N-tiles
+// 2g and 2g+1 of a wave hold the real and imaginary parts of the same 16
+// complex columns and every lane ends with whole complex results.  MFMA
+// operand layout: lane l holds A(l%16, l/16) and B(l/16, l%16); result
+// register r of lane l is D(4 r + l/16, l%16).
+//
+// K streams through double-buffered LDS in chunks of 16, stored [row][k]
+// with one column of padding (conflict-free fragment reads and stores).
+// The chunks k0 .. k0+15 that cover the workgroup's own rows also carry
+// X(i, :) for those rows, so sigma X and max |x| are taken from LDS there:
+// the epilogue makes no dependent loads.
+__global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
 {
-    constexpr int BM = 128, BNC = 64, BK = 16;
-    __shared__ double Hs[BK][BM];
-    __shared__ double Xs[BK][2 * BNC];
+    constexpr int BM = 128, BNC = 64, BK = 16, PK = BK + 1;
+    __shared__ double Hs[2][BM][PK];
+    __shared__ double Xs[2][2 * BNC][PK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int i0 = blockIdx.x * BM;
@@ -207,6 +79,16 @@ __global__ __launch_bounds__(256) void residual_mfma_kernel(ResidualArgs a)
         const int sid = a.list ? a.list[item] : item;
         xcol[e] = a.X + ((int64_t)sid * m + c) * a.ldx * 2;
     }
+    // this lane's two complex columns (g = 0, 1) and their shifts
+    double sgr[2], sgi[2], mx[2] = {0.0, 0.0};
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        const int w = w0 + wc * 32 + g * 16 + lane % 16;
+        const int item = (w < ncols ? w : 0) / m;
+        const int sid = a.list ? a.list[item] : item;
+        sgr[g] = a.shifts[2 * sid];
+        sgi[g] = a.shifts[2 * sid + 1];
+    }
     const int hr = tid % BM, hk = tid / BM;
     const int xk = tid % BK, xc = tid / BK;
     double hreg[8], xre[4], xim[4];
@@ -224,14 +106,14 @@ __global__ __launch_bounds__(256) void residual_mfma_kernel(ResidualArgs a)
             xim[e] = ok ? xcol[e][2 * (int64_t)k + 1] : 0.0;
         }
     };
-    auto lstore = [&]() {
+    auto lstore = [&](int b) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) Hs[hk + 2 * e][hr] = hreg[e];
+        for (int e = 0; e < 8; ++e) Hs[b][hr][hk + 2 * e] = hreg[e];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int cc = xc + 16 * e, g = cc / 16, j = cc % 16;
-            Xs[xk][32 * g + j] = xre[e];
-            Xs[xk][32 * g + 16 + j] = xim[e];
+            Xs[b][32 * g + j][xk] = xre[e];
+            Xs[b][32 * g + 16 + j][xk] = xim[e];
         }
     };
 
@@ -239,35 +121,65 @@ __global__ __launch_bounds__(256) void residual_mfma_kernel(ResidualArgs a)
     if (kstart < 0) kstart = 0;
     kstart = (kstart / BK) * BK;
     gload(kstart);
+    lstore(0);
+    if (kstart + BK < n) gload(kstart + BK);
+    __syncthreads();
+    int buf = 0;
     for (int k0 = kstart; k0 < n; k0 += BK) {
-        __syncthreads();
-        lstore();
-        __syncthreads();
-        if (k0 + BK < n) gload(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             double af[4], bf[4];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) af[mt] = Hs[kk + lane / 16][wr * 64 + mt * 16 + lane % 16];
+            for (int mt = 0; mt < 4; ++mt) af[mt] = Hs[buf][wr * 64 + mt * 16 + lane % 16][kk + lane / 16];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) bf[nt] = Xs[kk + lane / 16][wc * 64 + nt * 16 + lane % 16];
+            for (int nt = 0; nt < 4; ++nt) bf[nt] = Xs[buf][wc * 64 + nt * 16 + lane % 16][kk + lane / 16];
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mt], bf[nt], acc[mt][nt], 0, 0, 0);
         }
+        // the chunk holds X(i, :) for the 16 rows i = k0 .. k0+15: block mt of
+        // the waves with wr = (k0 - i0) / 64 (uniform per wave)
+        const int d = k0 - i0;
+        if (d >= 0 && d < BM && (d >> 6) == wr) {
+            const int mt = (d & 63) >> 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q != mt) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int kr = 4 * r + lane / 16;   // row k0 + kr
+#pragma unroll
+                    for (int g = 0; g < 2; ++g) {
+                        const double xr = Xs[buf][wc * 64 + 32 * g + lane % 16][kr];
+                        const double xi = Xs[buf][wc * 64 + 32 * g + 16 + lane % 16][kr];
+                        // H X - sigma X
+                        acc[q][2 * g][r] -= sgr[g] * xr - sgi[g] * xi;
+                        acc[q][2 * g + 1][r] -= sgr[g] * xi + sgi[g] * xr;
+                        const double ax = hypot(xr, xi);
+                        mx[g] = (ax > mx[g] || ax != ax) ? ax : mx[g];
+                    }
+                }
+            }
+        }
+        if (k0 + BK < n) {
+            // the other buffer was last read before the previous barrier
+            lstore(buf ^ 1);
+            if (k0 + 2 * BK < n) gload(k0 + 2 * BK);
+        }
+        __syncthreads();
+        buf ^= 1;
     }
 
-    // epilogue: Res = R - H X + sigma X and column maxima
+    // epilogue: Res = R - (H X - sigma X) and column maxima
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int w = w0 + wc * 32 + q * 16 + lane % 16;
-        double mr = 0.0, mx = 0.0;
+    for (int g = 0; g < 2; ++g) {
+        const int w = w0 + wc * 32 + g * 16 + lane % 16;
+        double mr = 0.0, mxg = mx[g];
         if (w < ncols) {
             const int item = w / m, c = w % m;
             const int sid = a.list ? a.list[item] : item;
-            const double sr = a.shifts[2 * sid], si = a.shifts[2 * sid + 1];
             const int64_t col = (int64_t)sid * m + c;
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
@@ -275,37 +187,33 @@ __global__ __launch_bounds__(256) void residual_mfma_kernel(ResidualArgs a)
                 for (int r = 0; r < 4; ++r) {
                     const int i = i0 + wr * 64 + mt * 16 + 4 * r + lane / 16;
                     if (i < n) {
-                        const double *px = a.X + (col * a.ldx + i) * 2;
-                        const double xr = px[0], xi = px[1];
-                        const double hxr = acc[mt][2 * q][r], hxi = acc[mt][2 * q + 1][r];
-                        const double rr = ((i < m) ? a.Rtop[c * m + i] : 0.0) - hxr + (sr * xr - si * xi);
-                        const double ri = -hxi + (sr * xi + si * xr);
+                        const double rr = ((i < m) ? a.Rtop[c * m + i] : 0.0) - acc[mt][2 * g][r];
+                        const double ri = -acc[mt][2 * g + 1][r];
                         if (a.Res) {
                             double *pr = a.Res + (col * a.ldr + i) * 2;
                             pr[0] = rr;
                             pr[1] = ri;
                         }
-                        const double ar = hypot(rr, ri), ax = hypot(xr, xi);
+                        const double ar = hypot(rr, ri);
                         mr = (ar > mr || ar != ar) ? ar : mr;
-                        mx = (ax > mx || ax != ax) ? ax : mx;
                     }
                 }
         }
         // lanes l, l+16, l+32, l+48 hold the same column
 #pragma unroll
         for (int off = 16; off < 64; off <<= 1) {
-            const double orr = __shfl_xor(mr, off), oxx = __shfl_xor(mx, off);
+            const double orr = __shfl_xor(mr, off), oxx = __shfl_xor(mxg, off);
             mr = (orr > mr || orr != orr) ? orr : mr;
-            mx = (oxx > mx || oxx != oxx) ? oxx : mx;
+            mxg = (oxx > mxg || oxx != oxx) ? oxx : mxg;
         }
         if (lane < 16 && w < ncols) {
             const int item = w / m, c = w % m;
             const int sid = a.list ? a.list[item] : item;
             const int64_t col = (int64_t)sid * m + c;
             if (mr != mr) mr = __longlong_as_double(0x7ff8000000000000LL);
-            if (mx != mx) mx = __longlong_as_double(0x7ff8000000000000LL);
+            if (mxg != mxg) mxg = __longlong_as_double(0x7ff8000000000000LL);
             atomic_max_nonneg(a.resmax + col, mr);
-            atomic_max_nonneg(a.xmax + col, mx);
+            atomic_max_nonneg(a.xmax + col, mxg);
         }
     }
 }

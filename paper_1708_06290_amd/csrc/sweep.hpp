@@ -268,11 +268,115 @@ __device__ __forceinline__ void pivot_row(const T (&wr)[R][M + 1], const T (&wi)
     }
 }
 
+// Pivot row when its slot RP is known at compile time: NP readlanes of that
+// slot only.
+template <typename T, int M, int R, int EM, int Q, bool DENSE, int RP>
+__device__ __forceinline__ void pivot_row_slot(const T (&wr)[R][M + 1], const T (&wi)[R][M + 1],
+                                               const T (&er)[R][EM], const T (&ei)[R][EM], int lp,
+                                               T (&pr)[M + 1], T (&pi)[M + 1], T (&pe_r)[EM], T (&pe_i)[EM])
+{
+    constexpr int NP = M + 1;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        pr[j] = readlane(wr[RP][(j + Q) % NP], lp);
+        pi[j] = readlane(wi[RP][(j + Q) % NP], lp);
+    }
+    if constexpr (DENSE) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            pe_r[c] = readlane(er[RP][c], lp);
+            pe_i[c] = readlane(ei[RP][c], lp);
+        }
+    }
+}
+
+// One tile step k (phase Q = k mod (m+1)); RP >= 0: the pivot is known to
+// be in slot RP, and only slots 0 .. RP are updated.
+template <typename T, int M, bool DENSE, int Q, int RP>
+__device__ __forceinline__ void tri_step(int k, int k_lo, int n, int lo, int lane, const T *H, int64_t ldh, T sgr,
+                                         T sgi, T *rf, int64_t tstride, T *Y, T *lds_rs,
+                                         T (&wr)[SweepShape<T, M, DENSE>::R][M + 1],
+                                         T (&wi)[SweepShape<T, M, DENSE>::R][M + 1],
+                                         T (&er)[SweepShape<T, M, DENSE>::R][SweepShape<T, M, DENSE>::EM],
+                                         T (&ei)[SweepShape<T, M, DENSE>::R][SweepShape<T, M, DENSE>::EM],
+                                         T (&nh)[SweepShape<T, M, DENSE>::R], bool &singular, bool &nonfinite)
+{
+    using Sh = SweepShape<T, M, DENSE>;
+    constexpr int R = Sh::R, TT = Sh::TT, S = Sh::S, EM = Sh::EM, NP = Sh::NP;
+    T ch[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) ch[r] = nh[r];
+    const int kn = k - 1 >= k_lo ? k - 1 : k_lo;
+    load_fresh<T, R>(H, ldh, n, lo, lane, kn - 1 - M, nh);
+    T pr[NP], pi[NP], per[EM], pei[EM];
+    if constexpr (RP < 0)
+        pivot_row<T, M, R, EM, Q, DENSE>(wr, wi, er, ei, k - lo, pr, pi, per, pei);
+    else
+        pivot_row_slot<T, M, R, EM, Q, DENSE, (RP < 0 ? 0 : RP)>(wr, wi, er, ei, (k - lo) & 63, pr,
+                                                              pi, per, pei);
+    T vr[M], vi[M], tau, br, bi, yr[EM], yi[EM];
+    make_refl<T, M>(pr, pi, vr, vi, tau, br, bi);
+    if (br == T(0) && bi == T(0)) singular = true;
+    if constexpr (DENSE) {
+        const T den = T(1) / fma(br, br, bi * bi);
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            yr[c] = (per[c] * br + pei[c] * bi) * den;
+            yi[c] = (pei[c] * br - per[c] * bi) * den;
+            if (!isfinite(yr[c]) || !isfinite(yi[c])) nonfinite = true;
+        }
+    } else {
+        yr[0] = T(0);
+        yi[0] = T(0);
+    }
+    if (lane == 0) {
+        T *p = const_cast<T *>(refl_slot<T>(rf, k, TT, tstride, S));
+        p[0] = tau;
+        p[1] = T(0);
+#pragma unroll
+        for (int j = 0; j < M; ++j) { p[2 + 2 * j] = vr[j]; p[3 + 2 * j] = vi[j]; }
+        if constexpr (DENSE) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                p[2 + 2 * M + 2 * c] = yr[c];
+                p[3 + 2 * M + 2 * c] = yi[c];
+                Y[2 * ((int64_t)c * n + k)] = yr[c];
+                Y[2 * ((int64_t)c * n + k) + 1] = yi[c];
+            }
+        }
+    }
+    T dr0 = T(0), di0 = T(0);
+    apply_step<T, M, R, EM, Q, (RP < 0 ? R : RP + 1), DENSE, !DENSE>(
+        wr, wi, er, ei, vr, vi, tau, yr, yi, ch, k - 1 - M, lo, lane, sgr, sgi, dr0, di0);
+    if constexpr (!DENSE) {
+        // leading block: R_sigma(i, k) for rows i < k (lanes of
+        // slot 0 in the top tile) and beta_k on the diagonal
+        if (k < M) {
+            if (lane < k) {
+                lds_rs[2 * (k * M + lane)] = dr0;
+                lds_rs[2 * (k * M + lane) + 1] = di0;
+            }
+            if (lane == 0) {
+                lds_rs[2 * (k * M + k)] = br;
+                lds_rs[2 * (k * M + k) + 1] = bi;
+            }
+        }
+    }
+}
+
 // The tile's own steps k = hi-1 .. lo: each pivot row is read out of its
 // owner lane, its reflector is formed, stored (lane 0) and applied to the
 // tile's rows above it.  The top tile records the leading block of R_sigma
 // (rows and columns < m) in lds_rs for the back substitution.
-template <typename T, int M, bool DENSE>
+//
+// SLOTS = true walks the steps slot by slot (pivots in slot R-1 first): the
+// pivot slot is then a compile-time constant, so the pivot row costs m+1
+// readlanes of one slot instead of all of them, and each step updates only
+// slots 0 .. RP, the ones that still hold rows above the pivot (rows in
+// higher slots are finished).  It unrolls the step body R times over; the
+// per-shift sweep keeps the plain form, because beside its stream phase the
+// R copies spill in FP32 (R = 8 there).
+template <typename T, int M, bool DENSE, bool SLOTS = false>
 __device__ __forceinline__ void tri_phase(int n, int lo, int hi, int lane, const T *H, int64_t ldh, T sgr, T sgi,
                                           T *rf, int64_t tstride, T *Y, T *lds_rs,
                                           T (&wr)[SweepShape<T, M, DENSE>::R][M + 1],
@@ -288,67 +392,31 @@ __device__ __forceinline__ void tri_phase(int n, int lo, int hi, int lane, const
         const int k_hi = hi - 1, k_lo = k_end;
         T nh[R];
         load_fresh<T, R>(H, ldh, n, lo, lane, k_hi - 1 - M, nh);
-        const int kg0 = k_hi + (M - k_hi % NP);   // group top: k = M (mod m+1)
-        for (int kg = kg0; kg >= k_lo; kg -= NP) {
-            static_for<NP>([&](auto sc) {
-                constexpr int st = decltype(sc)::value;
-                constexpr int Q = M - st;
-                const int k = kg - st;
-                if (k <= k_hi && k >= k_lo) {
-                    T ch[R];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) ch[r] = nh[r];
-                    const int kn = k - 1 >= k_lo ? k - 1 : k_lo;
-                    load_fresh<T, R>(H, ldh, n, lo, lane, kn - 1 - M, nh);
-                    T pr[NP], pi[NP], per[EM], pei[EM];
-                    pivot_row<T, M, R, EM, Q, DENSE>(wr, wi, er, ei, k - lo, pr, pi, per, pei);
-                    T vr[M], vi[M], tau, br, bi, yr[EM], yi[EM];
-                    make_refl<T, M>(pr, pi, vr, vi, tau, br, bi);
-                    if (br == T(0) && bi == T(0)) singular = true;
-                    if constexpr (DENSE) {
-                        const T den = T(1) / fma(br, br, bi * bi);
-#pragma unroll
-                        for (int c = 0; c < M; ++c) {
-                            yr[c] = (per[c] * br + pei[c] * bi) * den;
-                            yi[c] = (pei[c] * br - per[c] * bi) * den;
-                            if (!isfinite(yr[c]) || !isfinite(yi[c])) nonfinite = true;
-                        }
-                    } else {
-                        yr[0] = T(0);
-                        yi[0] = T(0);
-                    }
-                    if (lane == 0) {
-                        T *p = const_cast<T *>(refl_slot<T>(rf, k, TT, tstride, S));
-                        p[0] = tau;
-                        p[1] = T(0);
-#pragma unroll
-                        for (int j = 0; j < M; ++j) { p[2 + 2 * j] = vr[j]; p[3 + 2 * j] = vi[j]; }
-                        if constexpr (DENSE) {
-#pragma unroll
-                            for (int c = 0; c < M; ++c) {
-                                p[2 + 2 * M + 2 * c] = yr[c];
-                                p[3 + 2 * M + 2 * c] = yi[c];
-                                Y[2 * ((int64_t)c * n + k)] = yr[c];
-                                Y[2 * ((int64_t)c * n + k) + 1] = yi[c];
-                            }
-                        }
-                    }
-                    T dr0 = T(0), di0 = T(0);
-                    apply_step<T, M, R, EM, Q, R, DENSE, !DENSE>(wr, wi, er, ei, vr, vi, tau, yr, yi, ch,
-                                                                 k - 1 - M, lo, lane, sgr, sgi, dr0, di0);
-                    if constexpr (!DENSE) {
-                        // leading block: R_sigma(i, k) for rows i < k (lanes of
-                        // slot 0 in the top tile) and beta_k on the diagonal
-                        if (k < M) {
-                            if (lane < k) {
-                                lds_rs[2 * (k * M + lane)] = dr0;
-                                lds_rs[2 * (k * M + lane) + 1] = di0;
-                            }
-                            if (lane == 0) {
-                                lds_rs[2 * (k * M + k)] = br;
-                                lds_rs[2 * (k * M + k) + 1] = bi;
-                            }
-                        }
+        if constexpr (!SLOTS) {
+            const int kg0 = k_hi + (M - k_hi % NP);   // group top: k = M (mod m+1)
+            for (int kg = kg0; kg >= k_lo; kg -= NP) {
+                static_for<NP>([&](auto sc) {
+                    constexpr int st = decltype(sc)::value;
+                    const int k = kg - st;
+                    if (k <= k_hi && k >= k_lo)
+                        tri_step<T, M, DENSE, M - st, -1>(k, k_lo, n, lo, lane, H, ldh, sgr, sgi, rf, tstride, Y,
+                                                          lds_rs, wr, wi, er, ei, nh, singular, nonfinite);
+                });
+            }
+        } else {
+            static_for<R>([&](auto rc) {
+                constexpr int RP = R - 1 - decltype(rc)::value;
+                const int s_lo = max(k_lo, lo + RP * kWave), s_hi = min(k_hi, lo + RP * kWave + kWave - 1);
+                if (s_hi >= s_lo) {
+                    const int kg0 = s_hi + (M - s_hi % NP);
+                    for (int kg = kg0; kg >= s_lo; kg -= NP) {
+                        static_for<NP>([&](auto sc) {
+                            constexpr int st = decltype(sc)::value;
+                            const int k = kg - st;
+                            if (k <= s_hi && k >= s_lo)
+                                tri_step<T, M, DENSE, M - st, RP>(k, k_lo, n, lo, lane, H, ldh, sgr, sgi, rf, tstride,
+                                                                  Y, lds_rs, wr, wi, er, ei, nh, singular, nonfinite);
+                        });
                     }
                 }
             });
@@ -550,7 +618,7 @@ __device__ __forceinline__ void sweep_body(const SweepItem<T> &it, T *lds_refl, 
         }
 
         // ---- produce this tile's reflectors: steps hi-1 .. lo ------------------
-        tri_phase<T, M, DENSE>(n, lo, hi, lane, H, ldh, sgr, sgi, rf, tstride, Y, lds_rs, wr, wi, er, ei, singular,
+        tri_phase<T, M, DENSE, false>(n, lo, hi, lane, H, ldh, sgr, sgi, rf, tstride, Y, lds_rs, wr, wi, er, ei, singular,
                                nonfinite);
 
         // this tile's reflector stores complete before the next tile loads them

@@ -47,6 +47,29 @@ def sweep_flops(n: int, m: int) -> float:
     return (8.0 * m + 2.0) * n * n
 
 
+def measured_traffic():
+    """HBM bytes per launch of the solver kernels, from the rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes recorded in profiles/hbm_traffic.txt
+    (scaled by a plain device copy of known size).  A kernel's figure is used
+    only while its source file still hashes to the recorded value; otherwise
+    the counters describe an older kernel and traffic is null."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return {}
+    out = {}
+    for name, k in rec.get("kernels", {}).items():
+        try:
+            sha = hashlib.sha256(open(os.path.join(ROOT, k["source"]), "rb").read()).hexdigest()
+        except OSError:
+            continue
+        if sha == k.get("source_sha256"):
+            out[name] = k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+    return out
+
+
 def tile_rows(m: int) -> int:
     """Row-tile height of the FP64 sweep kernels: 64 lanes x rows per lane,
     where a lane keeps 144 VGPRs of window (2(m+1) doubles per row)."""
@@ -100,6 +123,8 @@ def parse():
                     help="requests per load level in the serving leg (0 = skip the leg)")
     ap.add_argument("--serve-scale", type=float, default=1.0, help="scale n of the serving systems")
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy 512 MiB once before the solves (a known-size kernel for HBM counters)")
     return ap.parse_args()
 
 
@@ -143,6 +168,14 @@ def main():
     status = torch.empty(s, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
+    if args.copy_calibration:
+        # a plain device copy of 512 MiB: its FETCH_SIZE / WRITE_SIZE readings
+        # scale the counters of the solver kernels to bytes
+        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     results = {}
     modes = ["fp64", "mixed"] if args.mode == "both" else [args.mode]
     for mode_name in modes:
@@ -202,12 +235,15 @@ def main():
             ("residual_mfma_kernel", "mfma", ph.get("residual_ms", 0.0), calls.get("residual_calls", 0),
              residual_flops(n, m) * s),
         ]
+        traffic = measured_traffic()
         for name, bound, ms, nl, fl in cand:
             if ms <= 0 or nl <= 0:
                 continue
             achieved = fl / (ms * 1e-3) / 1e12
+            tb = traffic.get(name)
             kernels[name] = {"bound": bound, "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
-                             "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                             "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                             "traffic": None if tb is None else round(tb),
                              "ms_per_step": round(ms, 3), "launches_per_step": nl,
                              "avg_launch_ms": round(ms / nl, 4), "flops_per_launch": fl / nl}
         if kernels:

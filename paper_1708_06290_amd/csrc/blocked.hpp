@@ -297,8 +297,24 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgs a)
     __shared__ double Bs[2][BN][PK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
     const int lo = a.lo, K = a.K;
+    // Tile order.  Workgroup L of the 1-D grid runs on XCD L mod 8; each XCD
+    // takes a contiguous chunk of the tile sequence, which walks groups of
+    // 8 row tiles column by column.  The workgroups resident on one XCD then
+    // share 8 row tiles of H and a few column tiles of Bm in its L2 (this
+    // halves the kernel's HBM reads against a row-major launch order).
+    int i0, j0;
+    {
+        const int nx = a.ncols / BN, ny = (lo + BM - 1) / BM, T = nx * ny;
+        const int L = blockIdx.x, xcd = L & 7, li = L >> 3;
+        const int per = T >> 3, rem = T & 7;
+        const int g = xcd * per + min(xcd, rem) + li;
+        constexpr int GR = 8;
+        const int grp = g / (GR * nx), r = g - grp * GR * nx;
+        const int rows = min(GR, ny - grp * GR);
+        i0 = (grp * GR + r % rows) * BM;
+        j0 = (r / rows) * BN;
+    }
     const double *Ab = a.H + (int64_t)a.c0 * a.ldh;
 
     zupd_dbl4 acc[4][4];

@@ -28,7 +28,7 @@ bool launch_blk_tri(int m, const BlkTriArgs &a, hipStream_t st)
 
 bool launch_zupd(int m, const ZupdArgs &a, hipStream_t st)
 {
-    const dim3 grid((unsigned)(a.ncols / 128), (unsigned)((a.lo + 127) / 128));
+    const dim3 grid((unsigned)((a.ncols / 128) * ((a.lo + 127) / 128)));
     switch (blk_width(m)) {
     case 2: hipLaunchKernelGGL((zupd_kernel<2>), grid, dim3(256), 0, st, a); return true;
     case 4: hipLaunchKernelGGL((zupd_kernel<4>), grid, dim3(256), 0, st, a); return true;

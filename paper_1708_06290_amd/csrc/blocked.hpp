@@ -424,9 +424,10 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgs a)
                 double v = acc[mt][nt][r];
                 if (i >= lo - m) {
                     const int w = j / W, q = j % W;
-                    if (w < a.count && q < 2 * m) {
-                        const int sid = a.list ? a.list[w] : w;
-                        const double sr = a.shifts[2 * sid], si = a.shifts[2 * sid + 1];
+                    const int sid = w < a.count ? (a.list ? a.list[w] : w) : 0;
+                    const double sr = a.shifts[2 * sid], si = a.shifts[2 * sid + 1];
+                    // a non-finite sigma has a zero transform and keeps Z zero
+                    if (w < a.count && q < 2 * m && isfinite(sr) && isfinite(si)) {
                         const int c = q < m ? q : q - m;
                         const int p = i - (lo - m);
                         const double ur = a.Bm[(int64_t)(w * W + c) * a.ldb + p];

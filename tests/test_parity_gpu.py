@@ -62,6 +62,13 @@ CASES = [
     (400, 5, 1, 3, 16),
     (333, 7, 4, 3, 17),
     (530, 11, 2, 2, 18),
+    # several full row tiles, so the all-shift update runs with carried
+    # columns for every per-shift column width (2m rounded up to 2, 4, 8, 16,
+    # 32; (1100, 2) above covers 4)
+    (1300, 1, 1, 3, 19),
+    (1200, 4, 2, 3, 20),
+    (1100, 6, 3, 2, 21),
+    (400, 16, 4, 2, 22),
 ]
 
 
@@ -198,10 +205,13 @@ def test_fp32_refine_matches_oracle():
         assert oracle.backward_error(H, R, X[:, j * m:(j + 1) * m], sg) <= ETA_TOL
 
 
-def test_batch_invariance_and_determinism():
+# single row tile (n = 400, m = 4) and several tiles with narrow shifts that
+# share MFMA blocks (m = 2: 4 shifts per 16-column block; m = 4: 2)
+@pytest.mark.parametrize("n,m", [(400, 4), (1100, 2), (1200, 4)])
+def test_batch_invariance_and_determinism(n, m):
     _need_gpu()
     import paper_1708_06290_amd as ss
-    A, B, C = workloads.system(400, 4, 2, 41)
+    A, B, C = workloads.system(n, m, 2, 41)
     shifts = workloads.imag_axis_shifts(1e-2, 1e2, 9)
     sysm = ss.System(A, B, C)
     r1 = sysm.solve(shifts)
@@ -209,4 +219,25 @@ def test_batch_invariance_and_determinism():
     r3 = sysm.solve(shifts[3:5])
     X1, X2, X3 = (r.X.cpu().numpy() for r in (r1, r2, r3))
     assert np.array_equal(X1, X2)
-    assert np.array_equal(X1[:, 12:20], X3)
+    assert np.array_equal(X1[:, 3 * m:5 * m], X3)
+
+
+def test_nonfinite_shift_stays_confined():
+    """A NaN shift next to good ones in the same MFMA block (m = 2) is flagged
+    and leaves its neighbours' results bitwise unchanged."""
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    n, m = 1100, 2
+    A, B, C = workloads.system(n, m, 1, 43)
+    good = workloads.imag_axis_shifts(1e-1, 1e1, 7)
+    mixed = np.concatenate([good[:3], [complex(np.nan, 1.0)], good[3:]])
+    sysm = ss.System(A, B, C)
+    ra = sysm.solve(good)
+    rb = sysm.solve(mixed)
+    torch.cuda.synchronize()
+    st = rb.status.cpu().numpy()
+    assert st[3] == ss.SHS_STATUS_NONFINITE, st
+    assert (np.delete(st, 3) == 0).all(), st
+    Xa, Xb = ra.X.cpu().numpy(), rb.X.cpu().numpy()
+    keep = np.concatenate([np.arange(0, 3 * m), np.arange(4 * m, 8 * m)])
+    assert np.array_equal(Xa, Xb[:, keep])

@@ -221,8 +221,11 @@ int shs_last_timings(const shs_handle *h, shs_timings_t *out);
  * runs shift requests from many clients.  Worker threads, one per HIP stream,
  * take work as soon as they are free: FP64 requests that are waiting are
  * batched into one launch of the work-item kernel (shifts of different
- * systems, with different n and m, in the same launch), a mixed-precision
- * request runs as one shs_solve on its worker's stream.  A request is
+ * systems, with different n and m, in the same launch), unless one shift is
+ * too much work for one wavefront (see blocked_flops): such a request, like
+ * a mixed-precision one, runs as one shs_solve on its worker's stream.  A
+ * request's route depends only on its system and mode, so its results are
+ * the same alone or in any mix.  A request is
  * admitted only when its workspace (shs_solve_workspace bytes) fits in what
  * is left of the device-memory budget; requests that arrive while others
  * run are admitted as workers and memory free up, so their work overlaps on
@@ -240,7 +243,12 @@ typedef struct shs_server_config {
     int64_t budget_bytes;   /* device-memory budget for request workspaces */
     int32_t max_batch;      /* most requests per FP64 batch (>= 1) */
     int32_t flags;          /* reserved, 0 */
-    int64_t reserved[4];
+    /* FP64 requests whose per-shift sweep work (8m+2) n^2 flops exceeds this
+     * run alone through shs_solve's blocked sweep instead of the work-item
+     * kernel (0: the default, 7.7e8 flops, about 20 ms of one wavefront);
+     * negative: never. */
+    double blocked_flops;
+    int64_t reserved[3];
 } shs_server_config;
 
 typedef struct shs_server_stats_t {

@@ -140,8 +140,8 @@ class Request:
 class Server:
     """Continuous-batching server over resident systems (see shs_server_* in shiftsolve.h)."""
 
-    def __init__(self, streams=4, budget_bytes=64 << 30, max_batch=64):
-        self.handle = shs_server_create(streams, budget_bytes, max_batch)
+    def __init__(self, streams=4, budget_bytes=64 << 30, max_batch=64, blocked_flops=0.0):
+        self.handle = shs_server_create(streams, budget_bytes, max_batch, blocked_flops)
         self.systems = []
 
     def register(self, system: "System") -> int:

@@ -60,7 +60,8 @@ class _Timings(ctypes.Structure):
 
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_int32), ("streams", ctypes.c_int32), ("budget_bytes", ctypes.c_int64),
-                ("max_batch", ctypes.c_int32), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int64 * 4)]
+                ("max_batch", ctypes.c_int32), ("flags", ctypes.c_int32), ("blocked_flops", ctypes.c_double),
+                ("reserved", ctypes.c_int64 * 3)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -252,10 +253,10 @@ def shs_destroy(h):
 # serving
 # ---------------------------------------------------------------------------
 
-def shs_server_create(streams=4, budget_bytes=64 << 30, max_batch=64):
+def shs_server_create(streams=4, budget_bytes=64 << 30, max_batch=64, blocked_flops=0.0):
     lib = _load()
     cfg = _ServerConfig(abi_version=SHS_ABI_VERSION, streams=streams, budget_bytes=budget_bytes,
-                        max_batch=max_batch)
+                        max_batch=max_batch, blocked_flops=blocked_flops)
     srv = ctypes.c_void_p()
     _check("shs_server_create", lib.shs_server_create(ctypes.byref(cfg), ctypes.byref(srv)))
     return srv

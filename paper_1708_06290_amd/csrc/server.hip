@@ -43,6 +43,7 @@ struct Request {
     int64_t ldx = 0, ldg = 0;
     int32_t *status = nullptr;
     size_t footprint = 0;
+    bool alone = false;           // runs as its own shs_solve (mixed mode, or blocked FP64)
     Clock::time_point t_submit, t_done;
     int state = 0;                // 0 queued, 1 running, 2 done, 3 failed
     int error = 0;
@@ -70,6 +71,7 @@ struct shs_server {
     int device = 0;
     size_t budget = 0;
     int max_batch = 64;
+    double blocked_flops = 7.7e8;
     std::vector<shs_handle *> systems;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -88,7 +90,7 @@ struct shs_server {
 
     void worker(int wid);
     int run_fp64_batch(std::vector<std::shared_ptr<Request>> &batch, hipStream_t st);
-    int run_mixed(Request &r, hipStream_t st);
+    int run_alone(Request &r, hipStream_t st);
 };
 
 int shs_server::run_fp64_batch(std::vector<std::shared_ptr<Request>> &batch, hipStream_t st)
@@ -176,7 +178,7 @@ int shs_server::run_fp64_batch(std::vector<std::shared_ptr<Request>> &batch, hip
     return e == hipSuccess ? 0 : (e == hipErrorOutOfMemory ? SHS_ERR_NOMEM : SHS_ERR_HIP);
 }
 
-int shs_server::run_mixed(Request &r, hipStream_t st)
+int shs_server::run_alone(Request &r, hipStream_t st)
 {
     shs_handle *h = systems[r.sys];
     double *dsh = nullptr;
@@ -210,10 +212,10 @@ void shs_server::worker(int wid)
                         pending.pop_front();
                         batch.push_back(head);
                         fp = head->footprint;
-                        if (head->mode == SHS_MODE_FP64) {
-                            // every other waiting FP64 request that fits joins the launch
+                        if (!head->alone) {
+                            // every other waiting work-item request that fits joins the launch
                             for (auto it = pending.begin(); it != pending.end() && (int)batch.size() < max_batch;) {
-                                if ((*it)->mode == SHS_MODE_FP64 && in_use + fp + (*it)->footprint <= budget) {
+                                if (!(*it)->alone && in_use + fp + (*it)->footprint <= budget) {
                                     fp += (*it)->footprint;
                                     batch.push_back(*it);
                                     it = pending.erase(it);
@@ -231,7 +233,7 @@ void shs_server::worker(int wid)
             peak = std::max(peak, in_use);
             running += (int64_t)batch.size();
             for (auto &r : batch) r->state = 1;
-            if (batch[0]->mode == SHS_MODE_FP64) {
+            if (!batch[0]->alone) {
                 ++batches;
                 std::vector<int32_t> sy;
                 for (auto &r : batch) sy.push_back(r->sys);
@@ -239,7 +241,7 @@ void shs_server::worker(int wid)
                 max_sys = std::max<int64_t>(max_sys, std::unique(sy.begin(), sy.end()) - sy.begin());
             }
         }
-        const int rc = (batch[0]->mode == SHS_MODE_FP64) ? run_fp64_batch(batch, st) : run_mixed(*batch[0], st);
+        const int rc = batch[0]->alone ? run_alone(*batch[0], st) : run_fp64_batch(batch, st);
         const auto now = Clock::now();
         {
             std::lock_guard<std::mutex> lk(mu);
@@ -279,6 +281,7 @@ int shs_server_create(const shs_server_config *cfg, shs_server **out)
     hipGetDevice(&srv->device);
     srv->budget = (size_t)cfg->budget_bytes;
     srv->max_batch = cfg->max_batch;
+    if (cfg->blocked_flops != 0.0) srv->blocked_flops = cfg->blocked_flops;
     for (int i = 0; i < cfg->streams; ++i) {
         hipStream_t st;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -336,7 +339,11 @@ int shs_server_submit(shs_server *srv, int32_t sys_id, int64_t s, const double *
     r->ldg = ldg;
     r->eta = eta;
     r->status = status;
-    if (mode == SHS_MODE_FP64) {
+    // one shift of a big system is too much for one wavefront of the
+    // work-item kernel: such FP64 requests take the blocked solve
+    const double shift_flops = (8.0 * h->m + 2.0) * (double)h->n * (double)h->n;
+    r->alone = mode != SHS_MODE_FP64 || (srv->blocked_flops >= 0.0 && shift_flops > srv->blocked_flops);
+    if (!r->alone) {
         r->footprint = fp64_item_bytes(h, s);
     } else {
         size_t b = 0;

@@ -45,7 +45,9 @@ def test_mix_equals_alone_and_oracle():
     _need_gpu()
     import paper_1708_06290_amd as ss
     systems = _systems(ss)
-    srv = ss.Server(streams=3, budget_bytes=8 << 30)
+    # (400, 16) has 2.1e7 flops per shift: above the threshold it takes the
+    # blocked solve, the other three systems share work-item launches
+    srv = ss.Server(streams=3, budget_bytes=8 << 30, blocked_flops=1.5e7)
     ids = [srv.register(s) for s in systems]
     reqs = _requests(18)
     handles = []
@@ -58,7 +60,7 @@ def test_mix_equals_alone_and_oracle():
     assert st["completed"] == len(reqs) and st["failed"] == 0
     assert st["max_batch_systems"] >= 1
     # the same requests again, one at a time, on an idle server
-    solo = ss.Server(streams=3, budget_bytes=8 << 30)
+    solo = ss.Server(streams=3, budget_bytes=8 << 30, blocked_flops=1.5e7)
     solo_ids = [solo.register(s) for s in systems]
     for (sys_id, shifts, mode), res in zip(reqs, results):
         sysm = systems[sys_id]

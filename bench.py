@@ -78,18 +78,24 @@ def tile_rows(m: int) -> int:
 
 def blocked_flops(n: int, m: int):
     """Algorithmic flops of one shift in the blocked FP64 sweep, split into
-    the per-shift tile kernels and the all-shift update GEMMs.
+    the per-shift tile kernels and the all-shift update GEMMs, following the
+    library's schedule.
 
     Tile kernel of rows lo..hi-1: step k updates the k - lo tile rows above
-    it (16m+4 flops each, as in the unblocked sweep), and forming the block
+    it (16m+4 flops each, as in the unblocked sweep); forming the block
     transform applies the tile's n_b reflectors to m columns of length m+1
-    (16(m+1) flops per column and reflector).  Update of the rows above the
-    tile: real H(0:lo, K columns) times 2m real columns per shift (2 lo K 2m
-    flops), plus the carried part z M2 (2 lo (2m)^2) for all but the bottom
-    tile, whose K includes the m carried columns."""
+    (16(m+1) flops per column and reflector); the second tile of a pair also
+    multiplies n_b + 2m rows by a 2m x 2m matrix (M1_a M2_b and M2_a M2_b).
+    Updates: the bottom tile's rows above it get H (K = n_b + m columns)
+    times 2m real columns; above it, tiles come in pairs (a, b): b's n_b rows
+    get M_a (K = n_b) right after a, and all rows above b get M_a and M_b
+    together after b (K = 2 n_b); each of these also multiplies the carried
+    columns by a 2m x 2m matrix.  2 flops per multiply-add."""
     tr = tile_rows(m)
     ntiles = (n + tr - 1) // tr
     tile = upd = 0.0
+    w = 2 * m
+    first = True
     for t in range(ntiles - 1, -1, -1):
         lo, hi = t * tr, min(n, (t + 1) * tr)
         nb = hi - lo
@@ -97,9 +103,15 @@ def blocked_flops(n: int, m: int):
         if t == 0:
             continue
         tile += 16.0 * (m + 1) * m * nb
-        bottom = t == ntiles - 1
-        K = nb + m if bottom else nb
-        upd += 2.0 * lo * K * 2 * m + (0.0 if bottom else 2.0 * lo * (2 * m) ** 2)
+        if t == ntiles - 1:
+            upd += 2.0 * lo * (nb + m) * w
+        elif first:
+            upd += 2.0 * tr * nb * w + 2.0 * tr * w * w
+            first = False
+        else:
+            tile += 2.0 * (tr + w) * w * w
+            upd += 2.0 * lo * 2 * tr * w + 2.0 * lo * w * w
+            first = True
     return tile, upd
 
 

@@ -25,8 +25,18 @@
 //                   (stored for the Q* pass), then forms M_blk by applying
 //                   them to [I_m; 0] (lanes c < m, one column each, a sliding
 //                   (m+1)-row window) and writes it real-ified for the GEMM.
-//   zupd_kernel     the GEMM above for rows 0 .. lo-1, in place on Z.
+//   zupd_kernel     the GEMM above, in place on Z.
 // The top tile's kernel ends with the m x m back substitution, as before.
+//
+// Above the bottom tile the updates are paired: after the first tile a of a
+// pair only the next tile b's rows get M_a (they are needed next); after b,
+// every row above b gets both at once,
+//
+//   z <- H(:, fresh_b) M1_b + H(:, fresh_a) (M1_a M2_b) + z (M2_a M2_b),
+//
+// one GEMM with K = 2 n_b over the contiguous columns fresh_b, fresh_a.  The
+// second tile kernel forms M1_a M2_b and M2_a M2_b itself.  This halves the
+// passes over Z and doubles K per update launch.
 //
 // Z holds, for work item (shift) w, the carried columns of every row as 2m
 // real columns w W .. w W + 2m - 1 (real parts, then imaginary parts) of a
@@ -68,8 +78,15 @@ struct BlkTriArgs {
     double *Bm;                // M1 (and for the bottom tile M2) rows, column-major, ld ldb
     int64_t ldb;
     double *M2;                // per work item W x W real (row-major), non-bottom tiles
+    double *M2p;               // per work item W x W: M2 of the first tile of a pair
+    int pair;                  // 0: bottom tile; 1: first of a pair; 2: second of a pair
 };
 
+// Block-transform destinations by tile mode (n_b = TT rows of M1 per tile):
+//   bottom        Bm rows 0 .. n_b+m-1 (M1 and M2, K = n_b + m)
+//   first (a)     M1_a -> Bm rows TT .. 2TT-1, M2_a -> M2p
+//   second (b)    M1_b -> Bm rows 0 .. TT-1; rows TT .. 2TT-1 <- M1_a M2_b;
+//                 M2 <- M2_a M2_b
 template <int M>
 __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
 {
@@ -78,6 +95,7 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
     constexpr int R = Sh::R, TT = Sh::TT, S = Sh::S, NP = Sh::NP;
     constexpr int W = blk_width(M);
     __shared__ T lds_rs[2 * M * M];
+    __shared__ T lds_m2[W * W];   // M2_b of a second tile, real form
     const int item = blockIdx.x;
     if (item >= a.count) return;
     const int sid = a.list ? a.list[item] : item;
@@ -160,9 +178,12 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
         const int c = lane < M ? lane : 0;
         const int nb = hi - lo;
         const int K = bottom ? nb + M : nb;
-        double *bcr = a.Bm + (int64_t)(item * W + c) * a.ldb;
-        double *bci = a.Bm + (int64_t)(item * W + M + c) * a.ldb;
-        double *m2 = a.M2 + (int64_t)item * W * W;
+        const int boff = a.pair == 1 ? TT : 0;
+        double *bcr = a.Bm + (int64_t)(item * W + c) * a.ldb + boff;
+        double *bci = a.Bm + (int64_t)(item * W + M + c) * a.ldb + boff;
+        // M2 is assembled in LDS: a second tile uses it right here, a first
+        // tile copies it to M2p (the bottom tile has none: K covers it)
+        for (int e = lane; e < W * W; e += kWave) lds_m2[e] = T(0);
         // slots past hi - 1 are loaded from a clamped address and never used
         auto fetch = [&](int cb) {
 #pragma unroll
@@ -185,10 +206,10 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
             } else {
                 // real form of z M2: [zr zi] [[Re, Im], [-Im, Re]]
                 const int cp = p - nb;
-                m2[cp * W + c] = xr;
-                m2[cp * W + M + c] = xi;
-                m2[(M + cp) * W + c] = -xi;
-                m2[(M + cp) * W + M + c] = xr;
+                lds_m2[cp * W + c] = xr;
+                lds_m2[cp * W + M + c] = xi;
+                lds_m2[(M + cp) * W + c] = -xi;
+                lds_m2[(M + cp) * W + M + c] = xr;
             }
         };
         T ur[NP], ui[NP];
@@ -249,13 +270,47 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
                 if (p < nb + M) emit(p, ur[q], ui[q]);
             }
         }
+        // one wave: its LDS writes above are complete before these reads
+        if (a.pair == 1) {
+            double *pm = a.M2p + (int64_t)item * W * W;
+            for (int e = lane; e < W * W; e += kWave) pm[e] = lds_m2[e];
+        }
+        if (a.pair == 2) {
+            // rows TT .. 2TT-1: M1_a <- M1_a M2_b (real form), R rows per lane
+            double *bb = a.Bm + (int64_t)item * W * a.ldb + TT;
+#pragma unroll 1
+            for (int p = lane; p < TT; p += kWave) {
+                T nw[2 * M];
+#pragma unroll
+                for (int q = 0; q < 2 * M; ++q) nw[q] = T(0);
+#pragma unroll 1
+                for (int q = 0; q < 2 * M; ++q) {
+                    const T o = bb[(int64_t)q * a.ldb + p];
+#pragma unroll
+                    for (int qq = 0; qq < 2 * M; ++qq) nw[qq] = fma(o, lds_m2[q * W + qq], nw[qq]);
+                }
+#pragma unroll
+                for (int q = 0; q < 2 * M; ++q) bb[(int64_t)q * a.ldb + p] = nw[q];
+            }
+            // M2 <- M2_a M2_b
+            const double *pa = a.M2p + (int64_t)item * W * W;
+            double *pm = a.M2 + (int64_t)item * W * W;
+            for (int e = lane; e < 4 * M * M; e += kWave) {
+                const int k = e / (2 * M), qq = e % (2 * M);
+                T acc = T(0);
+#pragma unroll 1
+                for (int q = 0; q < 2 * M; ++q) acc = fma(pa[k * W + q], lds_m2[q * W + qq], acc);
+                pm[k * W + qq] = acc;
+            }
+        }
     }
 }
 
 struct ZupdArgs {
-    int lo;                    // rows 0 .. lo-1 are updated
+    int r0;                    // rows r0 .. lo-1 are updated
+    int lo;
     int c0;                    // first column of H in the block (lo - m)
-    int K;                     // rows of M_blk multiplying H (n_b, or n_b + m for the bottom tile)
+    int K;                     // rows of M_blk multiplying H (n_b + m bottom, n_b or 2 n_b otherwise)
     int m;
     int ncols;                 // columns of Z (W per work item, a multiple of 128)
     int count;                 // work items
@@ -305,14 +360,14 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgs a)
     // halves the kernel's HBM reads against a row-major launch order).
     int i0, j0;
     {
-        const int nx = a.ncols / BN, ny = (lo + BM - 1) / BM, T = nx * ny;
+        const int nx = a.ncols / BN, ny = (lo - a.r0 + BM - 1) / BM, T = nx * ny;
         const int L = blockIdx.x, xcd = L & 7, li = L >> 3;
         const int per = T >> 3, rem = T & 7;
         const int g = xcd * per + min(xcd, rem) + li;
         constexpr int GR = 8;
         const int grp = g / (GR * nx), r = g - grp * GR * nx;
         const int rows = min(GR, ny - grp * GR);
-        i0 = (grp * GR + r % rows) * BM;
+        i0 = a.r0 + (grp * GR + r % rows) * BM;
         j0 = (r / rows) * BN;
     }
     const double *Ab = a.H + (int64_t)a.c0 * a.ldh;

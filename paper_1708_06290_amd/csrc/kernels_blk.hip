@@ -28,7 +28,8 @@ bool launch_blk_tri(int m, const BlkTriArgs &a, hipStream_t st)
 
 bool launch_zupd(int m, const ZupdArgs &a, hipStream_t st)
 {
-    const dim3 grid((unsigned)((a.ncols / 128) * ((a.lo + 127) / 128)));
+    if (a.lo <= a.r0) return true;
+    const dim3 grid((unsigned)((a.ncols / 128) * ((a.lo - a.r0 + 127) / 128)));
     switch (blk_width(m)) {
     case 2: hipLaunchKernelGGL((zupd_kernel<2>), grid, dim3(256), 0, st, a); return true;
     case 4: hipLaunchKernelGGL((zupd_kernel<4>), grid, dim3(256), 0, st, a); return true;

@@ -118,7 +118,7 @@ struct Layout {
     size_t refl32 = 0, y32 = 0, e32 = 0, yd32 = 0, res = 0, scale = 0, eta_prev = 0, status2 = 0;
     // blocked FP64 sweep (FP64 mode): carried columns, block transforms
     bool blocked = false;
-    size_t zb = 0, bm = 0, m2 = 0;
+    size_t zb = 0, bm = 0, m2 = 0, m2p = 0;
     int64_t blk_ldb = 0, blk_cols = 0;
     size_t total = 0;
 };
@@ -144,10 +144,11 @@ bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
         if (!blk_geometry((int)m, &tr, &w)) return false;
         L->blocked = true;
         L->blk_cols = (w * s + 127) / 128 * 128;
-        L->blk_ldb = tr + m;
+        L->blk_ldb = 2 * tr + m;
         L->zb = take(sizeof(double) * n * L->blk_cols);
         L->bm = take(sizeof(double) * L->blk_ldb * L->blk_cols);
         L->m2 = take(sizeof(double) * (L->blk_cols / w) * w * w);
+        L->m2p = take(sizeof(double) * (L->blk_cols / w) * w * w);
     }
     if (mode == SHS_MODE_FP32_REFINE) {
         if (!geo(true, n, m, false, &g32s) || !geo(true, n, m, true, &g32d)) return false;
@@ -213,11 +214,14 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     const int ntiles = (n + tr - 1) / tr;
     const int64_t ncols = (w * count + 127) / 128 * 128;
     double *Zb = at<double>(work, L.zb), *Bm = at<double>(work, L.bm), *M2 = at<double>(work, L.m2);
+    double *M2p = at<double>(work, L.m2p);
     PhaseScope whole(h, PH_SWEEP, count, st);
     // columns past 2m of each shift, and of the padding shifts, stay zero
     hipError_t e = hipMemsetAsync(Bm, 0, sizeof(double) * L.blk_ldb * ncols, st);
     if (e != hipSuccess) return e;
     e = hipMemsetAsync(M2, 0, sizeof(double) * (ncols / w) * w * w, st);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(M2p, 0, sizeof(double) * (ncols / w) * w * w, st);
     if (e != hipSuccess) return e;
     BlkTriArgs ta{};
     ta.n = n;
@@ -238,6 +242,7 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     ta.Bm = Bm;
     ta.ldb = L.blk_ldb;
     ta.M2 = M2;
+    ta.M2p = M2p;
     ZupdArgs za{};
     za.m = m;
     za.ncols = (int)ncols;
@@ -251,8 +256,14 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     za.ldz = n;
     za.shifts = shifts;
     za.list = dlist;
+    // bottom tile: all rows above it at once (K = n_b + m, no Z yet); then
+    // pairs (a, b = a - 1): after a, only b's rows get M_a; after b, all rows
+    // above b get M_a and M_b together (K = 2 n_b)
+    bool first = true;
     for (int t = ntiles - 1; t >= 0; --t) {
+        const bool bottom = t == ntiles - 1;
         ta.t = t;
+        ta.pair = bottom ? 0 : (first ? 1 : 2);
         {
             PhaseScope ps(h, PH_TILE, count, st);
             if (!launch_blk_tri(m, ta, st)) return hipErrorInvalidValue;
@@ -261,8 +272,27 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
         const int lo = t * tr, hi = std::min(n, lo + tr);
         za.lo = lo;
         za.c0 = lo - m;
-        za.K = t == ntiles - 1 ? hi - lo + m : hi - lo;
-        za.has_zin = t == ntiles - 1 ? 0 : 1;
+        if (bottom) {
+            za.r0 = 0;
+            za.K = hi - lo + m;
+            za.has_zin = 0;
+            za.Bm = Bm;
+            za.M2 = M2;
+        } else if (first) {
+            za.r0 = lo - tr;   // the next tile's rows
+            za.K = tr;
+            za.has_zin = 1;
+            za.Bm = Bm + tr;
+            za.M2 = M2p;
+            first = false;
+        } else {
+            za.r0 = 0;
+            za.K = 2 * tr;
+            za.has_zin = 1;
+            za.Bm = Bm;
+            za.M2 = M2;
+            first = true;
+        }
         {
             PhaseScope ps(h, PH_UPDATE, count, st);
             if (!launch_zupd(m, za, st)) return hipErrorInvalidValue;

@@ -205,6 +205,24 @@ def test_fp32_refine_matches_oracle():
         assert oracle.backward_error(H, R, X[:, j * m:(j + 1) * m], sg) <= ETA_TOL
 
 
+# at least five row tiles, so the paired update (K = 2 n_b over all rows
+# above the second tile of a pair) runs for every per-shift column width;
+# checked in reduced coordinates, where the oracle is O(n^2 m) per shift
+@pytest.mark.parametrize("n,m", [(2100, 1), (2100, 2), (1800, 4), (1400, 6), (1300, 8), (700, 16)])
+def test_paired_update_matches_oracle(n, m):
+    _need_gpu()
+    print(f"paired n={n} m={m}", flush=True)
+    shifts = workloads.imag_axis_shifts(1e-2, 1e2, 3)
+    A, B, C, sysm, res = _run(n, m, 2, shifts, 60 + m)
+    assert (res.status.cpu().numpy() == 0).all()
+    assert (res.eta.cpu().numpy() <= ETA_TOL).all()
+    H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
+    X = res.X.cpu().numpy()
+    Xo, Go, _, _ = oracle.solve(H, R, Ct, shifts)
+    _check_against(X, Xo, m, np.ones(len(shifts), bool), what="X (reduced)")
+    _check_against(res.G.cpu().numpy(), Go, m, np.ones(len(shifts), bool), what="G")
+
+
 # single row tile (n = 400, m = 4) and several tiles with narrow shifts that
 # share MFMA blocks (m = 2: 4 shifts per 16-column block; m = 4: 2)
 @pytest.mark.parametrize("n,m", [(400, 4), (1100, 2), (1200, 4)])

@@ -380,6 +380,7 @@ hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const do
     ra.ldr = n;
     ra.resmax = resmax;
     ra.xmax = xmax;
+    if (s_list <= 0) return hipGetLastError();
     hipLaunchKernelGGL(residual_mfma_kernel, dim3(cdiv(n, 128), cdiv(s_list * m, 64)), dim3(256), 0, st, ra);
     hipLaunchKernelGGL(eta_kernel, dim3((unsigned)s_list), dim3(256), 0, st, (int)n, (int)m, (int)s_list, dlist,
                        shifts, (const double *)h->offrow, (const double *)h->diag, (const double *)h->rcolmax,

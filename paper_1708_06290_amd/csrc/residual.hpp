@@ -55,10 +55,14 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
     __shared__ double Xs[2][2 * BNC][PK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int i0 = blockIdx.x * BM;
-    const int w0 = blockIdx.y * BNC;
     const int ncols = a.count * a.m;
     const int n = a.n, m = a.m;
+    // The K loop runs downwards from the last row of H: row tiles of one
+    // column tile (consecutive workgroups, spread over the XCDs, so each XCD
+    // gets long and short K ranges alike) then read the same rows of X at the
+    // same time, since all their K ranges end at n.
+    const int i0 = blockIdx.x * BM;
+    const int w0 = blockIdx.y * BNC;
 
     shs_dbl4 acc[4][4];
 #pragma unroll
@@ -120,12 +124,13 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
     int kstart = i0 - m;
     if (kstart < 0) kstart = 0;
     kstart = (kstart / BK) * BK;
-    gload(kstart);
+    const int ktop = ((n - 1) / BK) * BK;   // chunk holding the last row of H
+    gload(ktop);
     lstore(0);
-    if (kstart + BK < n) gload(kstart + BK);
+    if (ktop - BK >= kstart) gload(ktop - BK);
     __syncthreads();
     int buf = 0;
-    for (int k0 = kstart; k0 < n; k0 += BK) {
+    for (int k0 = ktop; k0 >= kstart; k0 -= BK) {
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             double af[4], bf[4];
@@ -163,10 +168,10 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
                 }
             }
         }
-        if (k0 + BK < n) {
+        if (k0 - BK >= kstart) {
             // the other buffer was last read before the previous barrier
             lstore(buf ^ 1);
-            if (k0 + 2 * BK < n) gload(k0 + 2 * BK);
+            if (k0 - 2 * BK >= kstart) gload(k0 - 2 * BK);
         }
         __syncthreads();
         buf ^= 1;

@@ -70,51 +70,6 @@ def measured_traffic():
     return out
 
 
-def tile_rows(m: int) -> int:
-    """Row-tile height of the FP64 sweep kernels: 64 lanes x rows per lane,
-    where a lane keeps 144 VGPRs of window (2(m+1) doubles per row)."""
-    return 64 * max(1, min(8, 144 // (4 * (m + 1))))
-
-
-def blocked_flops(n: int, m: int):
-    """Algorithmic flops of one shift in the blocked FP64 sweep, split into
-    the per-shift tile kernels and the all-shift update GEMMs, following the
-    library's schedule.
-
-    Tile kernel of rows lo..hi-1: step k updates the k - lo tile rows above
-    it (16m+4 flops each, as in the unblocked sweep); forming the block
-    transform applies the tile's n_b reflectors to m columns of length m+1
-    (16(m+1) flops per column and reflector); the second tile of a pair also
-    multiplies n_b + 2m rows by a 2m x 2m matrix (M1_a M2_b and M2_a M2_b).
-    Updates: the bottom tile's rows above it get H (K = n_b + m columns)
-    times 2m real columns; above it, tiles come in pairs (a, b): b's n_b rows
-    get M_a (K = n_b) right after a, and all rows above b get M_a and M_b
-    together after b (K = 2 n_b); each of these also multiplies the carried
-    columns by a 2m x 2m matrix.  2 flops per multiply-add."""
-    tr = tile_rows(m)
-    ntiles = (n + tr - 1) // tr
-    tile = upd = 0.0
-    w = 2 * m
-    first = True
-    for t in range(ntiles - 1, -1, -1):
-        lo, hi = t * tr, min(n, (t + 1) * tr)
-        nb = hi - lo
-        tile += (16 * m + 4) * nb * (nb - 1) / 2.0
-        if t == 0:
-            continue
-        tile += 16.0 * (m + 1) * m * nb
-        if t == ntiles - 1:
-            upd += 2.0 * lo * (nb + m) * w
-        elif first:
-            upd += 2.0 * tr * nb * w + 2.0 * tr * w * w
-            first = False
-        else:
-            tile += 2.0 * (tr + w) * w * w
-            upd += 2.0 * lo * 2 * tr * w + 2.0 * lo * w * w
-            first = True
-    return tile, upd
-
-
 def residual_flops(n: int, m: int) -> float:
     """FP64 residual H X - sigma X for one shift: real H (upper part + m
     subdiagonals, ~n^2/2 nonzeros) times 2m real columns, 2 flops each."""
@@ -224,6 +179,7 @@ def main():
             "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
             "phase_ms_per_step": {k: v / args.steps for k, v in phase.items() if k.endswith("_ms")},
             "launches_per_step": {k: v / args.steps for k, v in phase.items() if k.endswith("_calls")},
+            "flops_per_step": {k: v / args.steps for k, v in phase.items() if k.endswith("_flops")},
             "refine_iterations": phase.get("refine_iterations", 0) / args.steps,
             "fallback_shifts": phase.get("fallback_shifts", 0) / args.steps,
         }
@@ -239,11 +195,13 @@ def main():
     if "fp64" in results:
         r = results["fp64"]
         ph, calls = r["phase_ms_per_step"], r["launches_per_step"]
-        tile_f, upd_f = blocked_flops(n, m)
+        # algorithmic flops of the launches the library made (per step)
+        tile_f = r["flops_per_step"].get("sweep_tile_flops", 0.0)
+        upd_f = r["flops_per_step"].get("sweep_update_flops", 0.0)
         w = 2 if m <= 1 else 4 if m <= 2 else 8 if m <= 4 else 16 if m <= 8 else 32
         cand = [
-            (f"zupd_kernel<{w}>", "mfma", ph.get("sweep_update_ms", 0.0), calls.get("sweep_update_calls", 0), upd_f * s),
-            (f"blk_tri_kernel<{m}>", "alu", ph.get("sweep_tile_ms", 0.0), calls.get("sweep_tile_calls", 0), tile_f * s),
+            (f"zupd_kernel<{w}>", "mfma", ph.get("sweep_update_ms", 0.0), calls.get("sweep_update_calls", 0), upd_f),
+            (f"blk_tri_kernel<{m}>", "alu", ph.get("sweep_tile_ms", 0.0), calls.get("sweep_tile_calls", 0), tile_f),
             ("residual_mfma_kernel", "mfma", ph.get("residual_ms", 0.0), calls.get("residual_calls", 0),
              residual_flops(n, m) * s),
         ]

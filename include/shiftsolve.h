@@ -208,6 +208,11 @@ typedef struct shs_timings_t {
     double sweep_tile_ms;         /* per-shift row-tile kernels */
     double sweep_update_ms;       /* all-shift update GEMMs */
     int64_t sweep_tile_calls, sweep_update_calls;
+    /* Algorithmic flops of those launches (2 per multiply-add): tile steps
+     * (16m+4 per row above each pivot), block transforms and group products;
+     * update GEMMs (H block times 2m real columns per shift, carried columns
+     * times 2m x 2m). */
+    double sweep_tile_flops, sweep_update_flops;
 } shs_timings_t;
 
 int shs_set_timing(shs_handle *h, int enable);

@@ -55,7 +55,8 @@ class _Timings(ctypes.Structure):
                                               "sweep32_shifts", "sweep32_dense_shifts", "refine_iterations",
                                               "fallback_shifts")] + \
                [(f, ctypes.c_double) for f in ("sweep_tile_ms", "sweep_update_ms")] + \
-               [(f, ctypes.c_int64) for f in ("sweep_tile_calls", "sweep_update_calls")]
+               [(f, ctypes.c_int64) for f in ("sweep_tile_calls", "sweep_update_calls")] + \
+               [(f, ctypes.c_double) for f in ("sweep_tile_flops", "sweep_update_flops")]
 
 
 class _ServerConfig(ctypes.Structure):

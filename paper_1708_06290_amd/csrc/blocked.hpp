@@ -28,15 +28,20 @@
 //   zupd_kernel     the GEMM above, in place on Z.
 // The top tile's kernel ends with the m x m back substitution, as before.
 //
-// Above the bottom tile the updates are paired: after the first tile a of a
-// pair only the next tile b's rows get M_a (they are needed next); after b,
-// every row above b gets both at once,
+// Above the bottom tile the updates are grouped by D tiles a_1, a_2, ...
+// (bottom to top): after a_k (k < D) only the next tile's rows get the
+// group's composite transform so far (they are needed next); after a_D,
+// every row above gets all D at once.  For two tiles a, b = a - 1,
 //
 //   z <- H(:, fresh_b) M1_b + H(:, fresh_a) (M1_a M2_b) + z (M2_a M2_b),
 //
-// one GEMM with K = 2 n_b over the contiguous columns fresh_b, fresh_a.  The
-// second tile kernel forms M1_a M2_b and M2_a M2_b itself.  This halves the
-// passes over Z and doubles K per update launch.
+// one GEMM over the contiguous columns fresh_b, fresh_a; in general K = k n_b
+// after a_k.  The composite's operand rows sit at the end of Bm, newest tile
+// first (so it lines up with H's columns): a_k writes M1 to rows
+// (D-k) n_b .. (D-k+1) n_b - 1 and multiplies the older rows below them by
+// its M2 in place, and the composite carried matrix M2_{a_1} ... M2_{a_k} is
+// formed alongside.  This divides the passes over Z by D and multiplies K
+// per update launch by D.
 //
 // Z holds, for work item (shift) w, the carried columns of every row as 2m
 // real columns w W .. w W + 2m - 1 (real parts, then imaginary parts) of a
@@ -78,15 +83,16 @@ struct BlkTriArgs {
     double *Bm;                // M1 (and for the bottom tile M2) rows, column-major, ld ldb
     int64_t ldb;
     double *M2;                // per work item W x W real (row-major), non-bottom tiles
-    double *M2p;               // per work item W x W: M2 of the first tile of a pair
-    int pair;                  // 0: bottom tile; 1: first of a pair; 2: second of a pair
+    const double *M2p;         // per work item W x W: composite M2 of the group so far (k >= 2)
+    double *M2q;               // per work item W x W: composite M2 including this tile
+    int gk;                    // 0: bottom tile; k = 1 .. D: k-th tile of a group
+    int D;                     // tiles per group; Bm holds D TT + m rows
 };
 
-// Block-transform destinations by tile mode (n_b = TT rows of M1 per tile):
+// Block-transform destinations (n_b = TT rows of M1 per tile):
 //   bottom        Bm rows 0 .. n_b+m-1 (M1 and M2, K = n_b + m)
-//   first (a)     M1_a -> Bm rows TT .. 2TT-1, M2_a -> M2p
-//   second (b)    M1_b -> Bm rows 0 .. TT-1; rows TT .. 2TT-1 <- M1_a M2_b;
-//                 M2 <- M2_a M2_b
+//   k-th of group M1 -> Bm rows (D-k) TT .. (D-k+1) TT - 1; rows below it,
+//                 up to D TT - 1, <- themselves times M2; M2q <- M2p M2
 template <int M>
 __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
 {
@@ -178,11 +184,11 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
         const int c = lane < M ? lane : 0;
         const int nb = hi - lo;
         const int K = bottom ? nb + M : nb;
-        const int boff = a.pair == 1 ? TT : 0;
+        const int boff = a.gk >= 1 ? (a.D - a.gk) * TT : 0;
         double *bcr = a.Bm + (int64_t)(item * W + c) * a.ldb + boff;
         double *bci = a.Bm + (int64_t)(item * W + M + c) * a.ldb + boff;
-        // M2 is assembled in LDS: a second tile uses it right here, a first
-        // tile copies it to M2p (the bottom tile has none: K covers it)
+        // M2 is assembled in LDS and used right here (the bottom tile has
+        // none: its K covers it)
         for (int e = lane; e < W * W; e += kWave) lds_m2[e] = T(0);
         // slots past hi - 1 are loaded from a clamped address and never used
         auto fetch = [&](int cb) {
@@ -271,15 +277,16 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
             }
         }
         // one wave: its LDS writes above are complete before these reads
-        if (a.pair == 1) {
-            double *pm = a.M2p + (int64_t)item * W * W;
+        if (a.gk == 1) {
+            double *pm = a.M2q + (int64_t)item * W * W;
             for (int e = lane; e < W * W; e += kWave) pm[e] = lds_m2[e];
         }
-        if (a.pair == 2) {
-            // rows TT .. 2TT-1: M1_a <- M1_a M2_b (real form), R rows per lane
-            double *bb = a.Bm + (int64_t)item * W * a.ldb + TT;
+        if (a.gk >= 2) {
+            // the older composite rows: B <- B M2 (real form)
+            const int r1 = (a.D - a.gk + 1) * TT, nrows = (a.gk - 1) * TT;
+            double *bb = a.Bm + (int64_t)item * W * a.ldb + r1;
 #pragma unroll 1
-            for (int p = lane; p < TT; p += kWave) {
+            for (int p = lane; p < nrows; p += kWave) {
                 T nw[2 * M];
 #pragma unroll
                 for (int q = 0; q < 2 * M; ++q) nw[q] = T(0);
@@ -292,9 +299,9 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
 #pragma unroll
                 for (int q = 0; q < 2 * M; ++q) bb[(int64_t)q * a.ldb + p] = nw[q];
             }
-            // M2 <- M2_a M2_b
+            // M2q <- M2p M2
             const double *pa = a.M2p + (int64_t)item * W * W;
-            double *pm = a.M2 + (int64_t)item * W * W;
+            double *pm = a.M2q + (int64_t)item * W * W;
             for (int e = lane; e < 4 * M * M; e += kWave) {
                 const int k = e / (2 * M), qq = e % (2 * M);
                 T acc = T(0);

@@ -34,6 +34,7 @@ struct shs_handle {
     std::vector<Mark> marks;
     std::vector<hipEvent_t> pool;
     int64_t refine_iterations = 0, fallback_shifts = 0;
+    double tile_flops = 0.0, update_flops = 0.0;   // algorithmic flops of the blocked sweep's launches
 };
 
 enum { PH_SWEEP = 0, PH_QSTAR, PH_RESIDUAL, PH_SWEEP32, PH_SWEEP32D, PH_OTHER, PH_TILE, PH_UPDATE, PH_COUNT };

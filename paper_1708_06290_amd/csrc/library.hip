@@ -118,12 +118,15 @@ struct Layout {
     size_t refl32 = 0, y32 = 0, e32 = 0, yd32 = 0, res = 0, scale = 0, eta_prev = 0, status2 = 0;
     // blocked FP64 sweep (FP64 mode): carried columns, block transforms
     bool blocked = false;
-    size_t zb = 0, bm = 0, m2 = 0, m2p = 0;
+    size_t zb = 0, bm = 0, m2 = 0, m2p = 0, m2q = 0;
     int64_t blk_ldb = 0, blk_cols = 0;
     size_t total = 0;
 };
 
 inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Row tiles per update group of the blocked FP64 sweep.
+constexpr int kBlkGroup = 4;
 
 bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
 {
@@ -144,11 +147,12 @@ bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
         if (!blk_geometry((int)m, &tr, &w)) return false;
         L->blocked = true;
         L->blk_cols = (w * s + 127) / 128 * 128;
-        L->blk_ldb = 2 * tr + m;
+        L->blk_ldb = kBlkGroup * tr + m;
         L->zb = take(sizeof(double) * n * L->blk_cols);
         L->bm = take(sizeof(double) * L->blk_ldb * L->blk_cols);
         L->m2 = take(sizeof(double) * (L->blk_cols / w) * w * w);
         L->m2p = take(sizeof(double) * (L->blk_cols / w) * w * w);
+        L->m2q = take(sizeof(double) * (L->blk_cols / w) * w * w);
     }
     if (mode == SHS_MODE_FP32_REFINE) {
         if (!geo(true, n, m, false, &g32s) || !geo(true, n, m, true, &g32d)) return false;
@@ -214,7 +218,7 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     const int ntiles = (n + tr - 1) / tr;
     const int64_t ncols = (w * count + 127) / 128 * 128;
     double *Zb = at<double>(work, L.zb), *Bm = at<double>(work, L.bm), *M2 = at<double>(work, L.m2);
-    double *M2p = at<double>(work, L.m2p);
+    double *M2p = at<double>(work, L.m2p), *M2q = at<double>(work, L.m2q);
     PhaseScope whole(h, PH_SWEEP, count, st);
     // columns past 2m of each shift, and of the padding shifts, stay zero
     hipError_t e = hipMemsetAsync(Bm, 0, sizeof(double) * L.blk_ldb * ncols, st);
@@ -222,6 +226,8 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     e = hipMemsetAsync(M2, 0, sizeof(double) * (ncols / w) * w * w, st);
     if (e != hipSuccess) return e;
     e = hipMemsetAsync(M2p, 0, sizeof(double) * (ncols / w) * w * w, st);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(M2q, 0, sizeof(double) * (ncols / w) * w * w, st);
     if (e != hipSuccess) return e;
     BlkTriArgs ta{};
     ta.n = n;
@@ -242,7 +248,7 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     ta.Bm = Bm;
     ta.ldb = L.blk_ldb;
     ta.M2 = M2;
-    ta.M2p = M2p;
+    ta.D = kBlkGroup;
     ZupdArgs za{};
     za.m = m;
     za.ncols = (int)ncols;
@@ -257,17 +263,32 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     za.shifts = shifts;
     za.list = dlist;
     // bottom tile: all rows above it at once (K = n_b + m, no Z yet); then
-    // pairs (a, b = a - 1): after a, only b's rows get M_a; after b, all rows
-    // above b get M_a and M_b together (K = 2 n_b)
-    bool first = true;
+    // groups of kBlkGroup tiles: after the k-th, the next tile's rows get the
+    // group's composite (K = k n_b); after the last, all rows above do
+    int k = 0;
+    double *m2cur = M2p, *m2nxt = M2q;   // composite M2: read, written
     for (int t = ntiles - 1; t >= 0; --t) {
         const bool bottom = t == ntiles - 1;
         ta.t = t;
-        ta.pair = bottom ? 0 : (first ? 1 : 2);
+        if (!bottom) ++k;
+        ta.gk = bottom ? 0 : k;
+        ta.M2p = m2cur;
+        ta.M2q = m2nxt;
         {
             PhaseScope ps(h, PH_TILE, count, st);
             if (!launch_blk_tri(m, ta, st)) return hipErrorInvalidValue;
         }
+        if (h->timing) {   // timing state is only touched when enabled
+            // steps: (16m+4) flops per row above the pivot in the tile; the
+            // block transform: n_b reflectors on m columns of length m+1; a
+            // group's k-th tile: its older composite rows and M2 times 2m x 2m
+            const double nb = std::min(n, t * tr + tr) - t * tr, w2 = 2.0 * m;
+            double f = (16.0 * m + 4.0) * nb * (nb - 1.0) / 2.0;
+            if (t > 0) f += 16.0 * (m + 1) * m * nb;
+            if (t > 0 && k >= 2) f += 2.0 * ((k - 1) * tr + w2) * w2 * w2;
+            h->tile_flops += f * (double)count;
+        }
+        if (!bottom) std::swap(m2cur, m2nxt);   // m2cur: composite including tile t
         if (t == 0) break;
         const int lo = t * tr, hi = std::min(n, lo + tr);
         za.lo = lo;
@@ -278,25 +299,30 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
             za.has_zin = 0;
             za.Bm = Bm;
             za.M2 = M2;
-        } else if (first) {
+        } else if (k < kBlkGroup) {
             za.r0 = lo - tr;   // the next tile's rows
-            za.K = tr;
+            za.K = k * tr;
             za.has_zin = 1;
-            za.Bm = Bm + tr;
-            za.M2 = M2p;
-            first = false;
+            za.Bm = Bm + (kBlkGroup - k) * tr;
+            za.M2 = m2cur;
         } else {
             za.r0 = 0;
-            za.K = 2 * tr;
+            za.K = kBlkGroup * tr;
             za.has_zin = 1;
             za.Bm = Bm;
-            za.M2 = M2;
-            first = true;
+            za.M2 = m2cur;
+            k = 0;
         }
         {
             PhaseScope ps(h, PH_UPDATE, count, st);
             if (!launch_zupd(m, za, st)) return hipErrorInvalidValue;
         }
+        // H(rows, K columns) times 2m real columns per shift, plus z times a
+        // 2m x 2m matrix when carried columns are read
+        if (h->timing)
+            h->update_flops +=
+                (2.0 * (za.lo - za.r0) * za.K * 2 * m + (za.has_zin ? 2.0 * (za.lo - za.r0) * 4.0 * m * m : 0.0)) *
+                (double)count;
     }
     return hipGetLastError();
 }
@@ -745,6 +771,7 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outp
         h->marks.clear();
         h->refine_iterations = 0;
         h->fallback_shifts = 0;
+        h->tile_flops = h->update_flops = 0.0;
     }
     bool owned = false;
     if (work) {
@@ -1007,6 +1034,8 @@ int shs_last_timings(const shs_handle *h, shs_timings_t *out)
     }
     out->refine_iterations = h->refine_iterations;
     out->fallback_shifts = h->fallback_shifts;
+    out->sweep_tile_flops = h->tile_flops;
+    out->sweep_update_flops = h->update_flops;
     return 0;
 }
 

@@ -205,13 +205,14 @@ def test_fp32_refine_matches_oracle():
         assert oracle.backward_error(H, R, X[:, j * m:(j + 1) * m], sg) <= ETA_TOL
 
 
-# at least five row tiles, so the paired update (K = 2 n_b over all rows
-# above the second tile of a pair) runs for every per-shift column width;
-# checked in reduced coordinates, where the oracle is O(n^2 m) per shift
-@pytest.mark.parametrize("n,m", [(2100, 1), (2100, 2), (1800, 4), (1400, 6), (1300, 8), (700, 16)])
-def test_paired_update_matches_oracle(n, m):
+# seven or more row tiles, so a full group update (K = 4 n_b over all rows
+# above the group's last tile) and the near updates before it run for every
+# per-shift column width; checked in reduced coordinates, where the oracle
+# is O(n^2 m) per shift
+@pytest.mark.parametrize("n,m", [(3300, 1), (3300, 2), (3000, 4), (2100, 6), (1700, 8), (900, 16)])
+def test_grouped_update_matches_oracle(n, m):
     _need_gpu()
-    print(f"paired n={n} m={m}", flush=True)
+    print(f"grouped n={n} m={m}", flush=True)
     shifts = workloads.imag_axis_shifts(1e-2, 1e2, 3)
     A, B, C, sysm, res = _run(n, m, 2, shifts, 60 + m)
     assert (res.status.cpu().numpy() == 0).all()

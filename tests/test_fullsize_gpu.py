@@ -1,0 +1,123 @@
+"""Full-size workloads on the GPU, in the configuration bench.py times.
+
+Every shift's backward error is certified (eta <= 1e-13, from the library's
+FP64 residual and, for sampled shifts, recomputed here), and sampled shifts
+are compared one by one with the oracle in reduced coordinates, where it is
+O(n^2 m) per shift.  The mixed form is checked against the FP64 form on all
+shifts of the n = 10^4 workload.  Shifts of the complex-plane grid pass
+through the spectrum, so that workload is judged by backward error, and the
+forward error only on grid points well outside the spectrum's disc.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ETA_TOL = 1e-13
+FWD_TOL = 1e-10
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1708_06290_amd  # noqa: F401
+
+
+def _system(wl):
+    import paper_1708_06290_amd as ss
+    A, B, C = workloads.system(wl.n, wl.m, wl.p, wl.seed)
+    dev = torch.device("cuda", 0)
+    sysm = ss.System(torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev), torch.from_numpy(C).to(dev))
+    del A, B, C
+    return sysm
+
+
+def _shifts(wl):
+    if wl.shifts_kind == "imag":
+        return workloads.imag_axis_shifts(wl.lo, wl.hi, wl.s)
+    return workloads.plane_grid_shifts()[:wl.s]
+
+
+def _check_samples(sysm, res, shifts, idx, m):
+    """Sampled shifts against the oracle on (H, R, Ct), and eta recomputed."""
+    H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
+    cols = np.concatenate([np.arange(j * m, (j + 1) * m) for j in idx])
+    X = res.X[:, torch.as_tensor(cols, device=res.X.device)].cpu().numpy()
+    G = res.G[:, torch.as_tensor(cols, device=res.G.device)].cpu().numpy()
+    Xo, Go, eta_o, st_o = oracle.solve(H, R, Ct, shifts[idx])
+    for q, j in enumerate(idx):
+        xo, xg = Xo[:, q * m:(q + 1) * m], X[:, q * m:(q + 1) * m]
+        err = np.abs(xg - xo).max()
+        assert err <= FWD_TOL * np.linalg.norm(xo), f"shift {j}: X error {err:.3e}"
+        go, gg = Go[:, q * m:(q + 1) * m], G[:, q * m:(q + 1) * m]
+        assert np.abs(gg - go).max() <= FWD_TOL * np.linalg.norm(go), f"shift {j}: G"
+        assert oracle.backward_error(H, R, xg, shifts[j]) <= ETA_TOL, f"shift {j}: eta"
+
+
+def _certified(res, allow_fallback=False):
+    import paper_1708_06290_amd as ss
+    st = res.status.cpu().numpy()
+    ok = [0, ss.SHS_STATUS_FALLBACK] if allow_fallback else [0]
+    assert np.isin(st, ok).all(), np.unique(st, return_counts=True)
+    eta = res.eta.cpu().numpy()
+    assert (eta <= ETA_TOL).all(), eta.max()
+
+
+def test_c2_fp64_full():
+    _need_gpu()
+    wl = workloads.C2
+    print(f"workload {wl.name}", flush=True)
+    sysm = _system(wl)
+    shifts = _shifts(wl)
+    res = sysm.solve(shifts)
+    torch.cuda.synchronize()
+    _certified(res)
+    idx = workloads.subset_indices(wl.s, 8)
+    _check_samples(sysm, res, shifts, idx, wl.m)
+    sysm.close()
+
+
+def test_c3_fp64_and_mixed_full():
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    wl = workloads.C3
+    print(f"workload {wl.name}", flush=True)
+    sysm = _system(wl)
+    shifts = _shifts(wl)
+    r64 = sysm.solve(shifts, mode=ss.SHS_MODE_FP64)
+    torch.cuda.synchronize()
+    _certified(r64)
+    idx = workloads.subset_indices(wl.s, 4)
+    _check_samples(sysm, r64, shifts, idx, wl.m)
+    rmx = sysm.solve(shifts, mode=ss.SHS_MODE_FP32_REFINE)
+    torch.cuda.synchronize()
+    _certified(rmx, allow_fallback=True)
+    # mixed against FP64, every shift, on the device
+    m = wl.m
+    d = (rmx.X - r64.X).abs().reshape(wl.n, wl.s, m).amax(dim=(0, 2))
+    ref = r64.X.abs().reshape(wl.n, wl.s, m).amax(dim=(0, 2))
+    rel = (d / ref).cpu().numpy()
+    print(f"mixed vs FP64: max relative difference {rel.max():.3e}", flush=True)
+    assert (rel <= FWD_TOL).all(), rel.max()
+    sysm.close()
+
+
+def test_c5_mixed_full():
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    wl = workloads.C5
+    print(f"workload {wl.name}", flush=True)
+    sysm = _system(wl)
+    shifts = _shifts(wl)
+    res = sysm.solve(shifts, mode=ss.SHS_MODE_FP32_REFINE)
+    torch.cuda.synchronize()
+    _certified(res, allow_fallback=True)
+    # grid points far outside the spectrum's disc (centre -1.5, radius ~1)
+    far = np.flatnonzero(np.abs(shifts + 1.5) > 2.2)
+    idx = far[np.linspace(0, len(far) - 1, 2).round().astype(int)]
+    _check_samples(sysm, res, shifts, idx, wl.m)
+    sysm.close()

@@ -32,7 +32,8 @@ if ROOT not in sys.path:
 
 import workloads  # noqa: E402
 
-FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (256 CU x 2.4 GHz x 128 flop/clk)
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector and matrix (256 CU x 2.4 GHz x 128 flop/clk)
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector, published (packed FP32); issue without packing is half
 HBM_PEAK_GBS = 8000.0
 
 
@@ -180,6 +181,7 @@ def main():
             "phase_ms_per_step": {k: v / args.steps for k, v in phase.items() if k.endswith("_ms")},
             "launches_per_step": {k: v / args.steps for k, v in phase.items() if k.endswith("_calls")},
             "flops_per_step": {k: v / args.steps for k, v in phase.items() if k.endswith("_flops")},
+            "shifts_per_step": {k: v / args.steps for k, v in phase.items() if k.endswith("_shifts")},
             "refine_iterations": phase.get("refine_iterations", 0) / args.steps,
             "fallback_shifts": phase.get("fallback_shifts", 0) / args.steps,
         }
@@ -219,6 +221,29 @@ def main():
         if kernels:
             top = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
             roof = {"kernel": top, **kernels[top]}
+    # the mixed form's kernels: per-shift FP32 sweeps (structured, then dense
+    # right-hand side for the corrections), FP64 residuals
+    mixed_kernels = {}
+    if "mixed" in results:
+        r = results["mixed"]
+        ph, calls = r["phase_ms_per_step"], r["launches_per_step"]
+        # shift-solves of the correction sweeps; each also gets one more residual
+        nd = r["shifts_per_step"].get("sweep32_dense_shifts", 0.0)
+        cand = [
+            (f"sweep_kernel<float,{m},false>", "alu", FP32_PEAK_TFLOPS, ph.get("sweep32_ms", 0.0),
+             calls.get("sweep32_calls", 0), sweep_flops(n, m) * s),
+            (f"sweep_kernel<float,{m},true>", "alu", FP32_PEAK_TFLOPS, ph.get("sweep32_dense_ms", 0.0),
+             calls.get("sweep32_dense_calls", 0), (12.0 * m + 6.0) * n * n * nd),
+            ("residual_mfma_kernel", "mfma", FP64_PEAK_TFLOPS, ph.get("residual_ms", 0.0),
+             calls.get("residual_calls", 0), residual_flops(n, m) * (s + nd)),
+        ]
+        for name, bound, peak, ms, nl, fl in cand:
+            if ms <= 0 or nl <= 0:
+                continue
+            achieved = fl / (ms * 1e-3) / 1e12
+            mixed_kernels[name] = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                                   "frac": round(achieved / peak, 4), "ms_per_step": round(ms, 3),
+                                   "launches_per_step": nl}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -247,6 +272,7 @@ def main():
                    "reduce_ms": round(info["reduce_ms"], 1)},
         "roofline": roof,
         "kernels": kernels,
+        "mixed_kernels": mixed_kernels,
         "cpu_baseline": cpu,
         "fp64": results.get("fp64"),
         "mixed": results.get("mixed"),

@@ -27,12 +27,13 @@ struct Inst {
     }
     static void qstar(bool dense_in, const QstarArgs<REAL_T> &a, hipStream_t st)
     {
-        constexpr int spw = kWave / MM;
-        const int blocks = (a.count + spw - 1) / spw;
-        if (dense_in)
+        if (dense_in) {
+            constexpr int spw = kWave / MM;
+            const int blocks = (a.count + spw - 1) / spw;
             hipLaunchKernelGGL((qstar_kernel<REAL_T, MM, true>), dim3(blocks), dim3(kWave), 0, st, a);
-        else
-            hipLaunchKernelGGL((qstar_kernel<REAL_T, MM, false>), dim3(blocks), dim3(kWave), 0, st, a);
+        } else if (a.count > 0) {
+            hipLaunchKernelGGL((qstar_wave_kernel<REAL_T, MM>), dim3(a.count), dim3(kWave), 0, st, a);
+        }
     }
 };
 

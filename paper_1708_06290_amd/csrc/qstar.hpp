@@ -153,4 +153,122 @@ __global__ __launch_bounds__(64) void qstar_kernel(QstarArgs<T> a)
     qstar_body<T, M, DENSE_IN>(a.n, active, c, rf, a.tile_rows, a.tile_stride, a.slot, Y, X, a.accumulate, sc);
 }
 
+// Structured right-hand side ([Y; 0], Y m x m), one wavefront per shift:
+// lanes c < m own column c as above, while the whole wave stages the
+// reflectors through LDS in chunks of whole phase groups (coalesced loads,
+// the next chunk in flight while the current one is used), so the serial
+// chain of n steps does not wait on memory.  The inner product v^* y is
+// summed in two interleaved partial sums to halve its dependence chain.
+template <typename T, int M>
+__global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a)
+{
+    constexpr int NP = M + 1;
+    constexpr int CE = 1536;                    // LDS elements per chunk
+    constexpr int PL = CE / kWave;
+    static_assert(CE % kWave == 0 && CE >= slot_elems(M, true) * NP, "chunk");
+    __shared__ T lds_ch[CE];
+    const int item = blockIdx.x;
+    if (item >= a.count || a.n < 1) return;
+    const int lane = threadIdx.x;
+    const int c = lane < M ? lane : 0;
+    const int n = a.n, S = a.slot;
+    const int CS = NP * ((CE / S) / NP);        // steps per chunk, >= m+1
+    const int ce_elems = CS * S;
+    const int sid = a.list ? a.list[item] : item;
+    const T *rf = a.refl + (int64_t)sid * a.refl_stride;
+    const T *Y = a.Y + (int64_t)sid * a.y_stride;
+    double *X = a.X + ((int64_t)sid * M + c) * a.ldx * 2;
+    const double sc = (a.accumulate && a.scale) ? a.scale[sid] : 1.0;
+    T pre[PL];
+    // slots past n-1 are read from slot n-1 and never used
+    auto fetch = [&](int cb) {
+#pragma unroll
+        for (int e = 0; e < PL; ++e) {
+            const int idx0 = e * kWave + lane;
+            const int idx = idx0 < ce_elems ? idx0 : ce_elems - 1;
+            const int ks = idx / S, el = idx - ks * S;
+            const int k = min(cb + ks, n - 1);
+            pre[e] = refl_slot<T>(rf, k, a.tile_rows, a.tile_stride, S)[el];
+        }
+    };
+    double yr[NP], yi[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) { yr[j] = 0.0; yi[j] = 0.0; }
+    // phase 0: logical j in slot j; row 0 is logical m
+    yr[M] = (double)Y[2 * (c * M)];
+    yi[M] = (double)Y[2 * (c * M) + 1];
+    const int k_last = n - 1 + M;   // steps k >= n only flush the window
+    fetch(0);
+    for (int cb = 0; cb <= k_last; cb += CS) {
+        __syncthreads();            // previous chunk fully read
+#pragma unroll
+        for (int e = 0; e < PL; ++e) {
+            const int idx = e * kWave + lane;
+            if (idx < ce_elems) lds_ch[idx] = pre[e];
+        }
+        __syncthreads();
+        if (cb + CS < n) fetch(cb + CS);
+        if (lane < M) {
+            const int ce = min(k_last + 1, cb + CS);
+            for (int kg = cb; kg < ce; kg += NP) {
+                static_for<NP>([&](auto qc) {
+                    constexpr int Q = decltype(qc)::value;   // k mod (m+1)
+                    const int k = kg + Q;
+                    if (k < ce) {
+                        if (k < n) {
+                            const T *pv = lds_ch + (k - cb) * S;
+                            const double tau = (double)pv[0];
+                            double vr[M], vi[M];
+#pragma unroll
+                            for (int j = 0; j < M; ++j) {
+                                vr[j] = (double)pv[2 + 2 * j];
+                                vi[j] = (double)pv[3 + 2 * j];
+                            }
+                            // d = v^* y over rows k-m .. k (v_m = 1)
+                            constexpr int pm = (M + Q) % NP;
+                            double dr0 = yr[pm], di0 = yi[pm], dr1 = 0.0, di1 = 0.0;
+#pragma unroll
+                            for (int j = 0; j < M; ++j) {
+                                const int p = (j + Q) % NP;
+                                if (j & 1) {
+                                    dr1 = fma(vr[j], yr[p], fma(vi[j], yi[p], dr1));
+                                    di1 = fma(vr[j], yi[p], fma(-vi[j], yr[p], di1));
+                                } else {
+                                    dr0 = fma(vr[j], yr[p], fma(vi[j], yi[p], dr0));
+                                    di0 = fma(vr[j], yi[p], fma(-vi[j], yr[p], di0));
+                                }
+                            }
+                            const double tr = tau * (dr0 + dr1), ti = tau * (di0 + di1);
+#pragma unroll
+                            for (int j = 0; j < M; ++j) {
+                                const int p = (j + Q) % NP;
+                                yr[p] = fma(-tr, vr[j], fma(ti, vi[j], yr[p]));
+                                yi[p] = fma(-tr, vi[j], fma(-ti, vr[j], yi[p]));
+                            }
+                            yr[pm] -= tr;
+                            yi[pm] -= ti;
+                        }
+                        // row k-m (logical 0, slot Q) is final
+                        const int row = k - M;
+                        if (row >= 0 && row < n) {
+                            double *px = X + 2 * (int64_t)row;
+                            if (a.accumulate) {
+                                px[0] += sc * yr[Q];
+                                px[1] += sc * yi[Q];
+                            } else {
+                                px[0] = yr[Q];
+                                px[1] = yi[Q];
+                            }
+                        }
+                        // row k+1 enters in the freed slot: [Y; 0]
+                        const int i = k + 1;
+                        yr[Q] = (i < M && i < n) ? (double)Y[2 * (c * M + i)] : 0.0;
+                        yi[Q] = (i < M && i < n) ? (double)Y[2 * (c * M + i) + 1] : 0.0;
+                    }
+                });
+            }
+        }
+    }
+}
+
 }  // namespace shs

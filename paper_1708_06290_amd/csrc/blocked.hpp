@@ -80,8 +80,8 @@ struct BlkTriArgs {
     int32_t *status;           // per shift id
     const double *Z;           // carried columns (see above), ld ldz
     int64_t ldz;
-    double *Bm;                // M1 (and for the bottom tile M2) rows, column-major, ld ldb
-    int64_t ldb;
+    double *Bm;                // M1 (and for the bottom tile M2) rows, row-major: row k at Bm + k ldb
+    int64_t ldb;               // row stride of Bm (columns of Z, a multiple of 128)
     double *M2;                // per work item W x W real (row-major), non-bottom tiles
     const double *M2p;         // per work item W x W: composite M2 of the group so far (k >= 2)
     double *M2q;               // per work item W x W: composite M2 including this tile
@@ -185,8 +185,10 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
         const int nb = hi - lo;
         const int K = bottom ? nb + M : nb;
         const int boff = a.gk >= 1 ? (a.D - a.gk) * TT : 0;
-        double *bcr = a.Bm + (int64_t)(item * W + c) * a.ldb + boff;
-        double *bci = a.Bm + (int64_t)(item * W + M + c) * a.ldb + boff;
+        // row p of the block transform is row boff + p of Bm; this shift's
+        // real and imaginary parts are its columns item W + c and item W + m + c
+        double *bcr = a.Bm + (int64_t)boff * a.ldb + item * W + c;
+        double *bci = bcr + M;
         // M2 is assembled in LDS and used right here (the bottom tile has
         // none: its K covers it)
         for (int e = lane; e < W * W; e += kWave) lds_m2[e] = T(0);
@@ -207,8 +209,8 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
         auto emit = [&](int p, T xr, T xi) {
             if (bad) xr = xi = T(0);
             if (p < K) {
-                bcr[p] = xr;
-                bci[p] = xi;
+                bcr[(int64_t)p * a.ldb] = xr;
+                bci[(int64_t)p * a.ldb] = xi;
             } else {
                 // real form of z M2: [zr zi] [[Re, Im], [-Im, Re]]
                 const int cp = p - nb;
@@ -284,20 +286,21 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
         if (a.gk >= 2) {
             // the older composite rows: B <- B M2 (real form)
             const int r1 = (a.D - a.gk + 1) * TT, nrows = (a.gk - 1) * TT;
-            double *bb = a.Bm + (int64_t)item * W * a.ldb + r1;
+            double *bb = a.Bm + (int64_t)r1 * a.ldb + item * W;
 #pragma unroll 1
             for (int p = lane; p < nrows; p += kWave) {
+                double *row = bb + (int64_t)p * a.ldb;
                 T nw[2 * M];
 #pragma unroll
                 for (int q = 0; q < 2 * M; ++q) nw[q] = T(0);
 #pragma unroll 1
                 for (int q = 0; q < 2 * M; ++q) {
-                    const T o = bb[(int64_t)q * a.ldb + p];
+                    const T o = row[q];
 #pragma unroll
                     for (int qq = 0; qq < 2 * M; ++qq) nw[qq] = fma(o, lds_m2[q * W + qq], nw[qq]);
                 }
 #pragma unroll
-                for (int q = 0; q < 2 * M; ++q) bb[(int64_t)q * a.ldb + p] = nw[q];
+                for (int q = 0; q < 2 * M; ++q) row[q] = nw[q];
             }
             // M2q <- M2p M2
             const double *pa = a.M2p + (int64_t)item * W * W;
@@ -314,17 +317,18 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
 }
 
 struct ZupdArgs {
-    int r0;                    // rows r0 .. lo-1 are updated
+    int r0;                    // rows r0 .. lo-1 are updated (r0 and lo even, lo - r0 >= 2)
     int lo;
     int c0;                    // first column of H in the block (lo - m)
-    int K;                     // rows of M_blk multiplying H (n_b + m bottom, n_b or 2 n_b otherwise)
+    int K;                     // rows of M_blk multiplying H (n_b + m bottom, k n_b otherwise)
     int m;
+    int n;                     // order of H: columns past n-1 are never read
     int ncols;                 // columns of Z (W per work item, a multiple of 128)
     int count;                 // work items
     int has_zin;               // 0 for the bottom tile (no carried columns in Z yet)
-    const double *H;
+    const double *H;           // ld ldh, even, 16-byte aligned columns
     int64_t ldh;
-    const double *Bm;
+    const double *Bm;          // row-major, row stride ldb; rows K .. K rounded up to 16 are zero
     int64_t ldb;
     const double *M2;
     double *Z;
@@ -334,6 +338,10 @@ struct ZupdArgs {
 };
 
 typedef double zupd_dbl4 __attribute__((ext_vector_type(4)));
+
+// LDS of zupd_kernel (dynamic): two stages of a 16 x 128 chunk of H^T rows
+// and of Bm rows.
+constexpr int kZupdLds = 2 * 2 * 16 * 128 * (int)sizeof(double);
 
 // Z(0:lo, :) <- H(0:lo, c0 : c0+K) Bm(0:K, :) + (per shift) Z M2, minus
 // sigma M1 on the rows whose diagonal is in the block.  128 x 128 tiles,
@@ -348,15 +356,26 @@ typedef double zupd_dbl4 __attribute__((ext_vector_type(4)));
 // tile kernel keeps every shift's Z finite (a shift with a non-finite sigma
 // gets a zero block transform), so the zeros never meet a NaN.  A
 // workgroup reads only its own tile of Z, all before it writes, so the
-// update is in place.  The main product streams K in chunks of 16 through
-// double-buffered LDS stored [row][k] with one column of padding, which
-// keeps the fragment reads and the stores free of bank conflicts.
+// update is in place.
+//
+// The main product streams K in chunks of 16 through two LDS stages that
+// the memory system fills directly (global_load_lds_dwordx4: each lane
+// moves two consecutive doubles of one row of the chunk, so neither operand
+// passes through registers).  Both operands sit in LDS k-major ([k][row]
+// and [k][column]), which is how H (column-major) and Bm (row-major) lie in
+// memory; the fragment reads of 16 consecutive rows or columns are free of
+// bank conflicts.  Rows of the tile at or past lo read row lo-2 and columns
+// past n-1 read column n-1: their products are never stored or meet zero
+// rows of Bm.  Each chunk's loads are issued right after the previous
+// chunk's fragments are in registers and waited for only after its 64
+// MFMAs.
 template <int W>
 __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgs a)
 {
-    constexpr int BM = 128, BN = 128, BK = 16, PK = BK + 1;
-    __shared__ double As[2][BM][PK];
-    __shared__ double Bs[2][BN][PK];
+    constexpr int BM = 128, BN = 128, BK = 16;
+    extern __shared__ double zupd_smem[];
+    auto As = reinterpret_cast<double (*)[BK][BM]>(zupd_smem);
+    auto Bs = reinterpret_cast<double (*)[BK][BN]>(zupd_smem + 2 * BK * BM);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int lo = a.lo, K = a.K;
@@ -377,7 +396,6 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgs a)
         i0 = a.r0 + (grp * GR + r % rows) * BM;
         j0 = (r / rows) * BN;
     }
-    const double *Ab = a.H + (int64_t)a.c0 * a.ldh;
 
     zupd_dbl4 acc[4][4];
 #pragma unroll
@@ -425,51 +443,48 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgs a)
     }
 
     // ---- main product: H(0:lo, c0 : c0+K) Bm -----------------------------------
-    double ra[8], rb[8];
-    auto gload = [&](int k0) {
+    // wave w moves rows k = 4w .. 4w+3 of each chunk of both operands
+    const int ia = min(i0 + 2 * lane, lo - 2);
+    const double *pa = a.H + ia;
+    const double *pb = a.Bm + j0 + 2 * lane;
+    auto issue = [&](int b, int k0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int i = i0 + (tid % BM), k = k0 + tid / BM + 2 * e;
-            ra[e] = (i < lo && k < K) ? Ab[(int64_t)k * a.ldh + i] : 0.0;
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int k = k0 + (tid % BK), j = j0 + tid / BK + 16 * e;
-            rb[e] = k < K ? a.Bm[(int64_t)j * a.ldb + k] : 0.0;
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * wave + e;
+            const int col = min(a.c0 + k0 + k, a.n - 1);
+            __builtin_amdgcn_global_load_lds((const void *)(pa + (int64_t)col * a.ldh),
+                                             (__attribute__((address_space(3))) void *)&As[b][k][0], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(pb + (int64_t)(k0 + k) * a.ldb),
+                                             (__attribute__((address_space(3))) void *)&Bs[b][k][0], 16, 0, 0);
         }
     };
-    auto lstore = [&](int b) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) As[b][tid % BM][tid / BM + 2 * e] = ra[e];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) Bs[b][tid / BK + 16 * e][tid % BK] = rb[e];
-    };
-    gload(0);
-    lstore(0);
-    if (BK < K) gload(BK);
+    const int nk = (K + BK - 1) / BK;
+    if (nk > 0) issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0x0070);   // vmcnt(0) lgkmcnt(0)
     __syncthreads();
-    int buf = 0;
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    for (int it = 0; it < nk; ++it) {
+        const int b = it & 1;
+        double af[4][4], bf[4][4];
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            double af[4], bf[4];
+        for (int s = 0; s < 4; ++s) {
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) af[mt] = As[buf][wr * 64 + mt * 16 + lane % 16][kk + lane / 16];
+            for (int mt = 0; mt < 4; ++mt) af[s][mt] = As[b][4 * s + lane / 16][wr * 64 + mt * 16 + lane % 16];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) bf[nt] = Bs[buf][wc * 64 + nt * 16 + lane % 16][kk + lane / 16];
+            for (int nt = 0; nt < 4; ++nt) bf[s][nt] = Bs[b][4 * s + lane / 16][wc * 64 + nt * 16 + lane % 16];
+        }
+        // the other stage was last read before the previous barrier
+        if (it + 1 < nk) issue(b ^ 1, (it + 1) * BK);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mt], bf[nt], acc[mt][nt], 0, 0, 0);
-        }
-        if (k0 + BK < K) {
-            // the other buffer was last read before the previous barrier
-            lstore(buf ^ 1);
-            if (k0 + 2 * BK < K) gload(k0 + 2 * BK);
-        }
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s][mt], bf[s][nt], acc[mt][nt], 0, 0, 0);
+        // keep the wait for the next chunk behind this chunk's products
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0x0070);
         __syncthreads();
-        buf ^= 1;
     }
 
     // ---- epilogue: sigma on the block's diagonal rows, store ----------------
@@ -492,8 +507,8 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgs a)
                     if (w < a.count && q < 2 * m && isfinite(sr) && isfinite(si)) {
                         const int c = q < m ? q : q - m;
                         const int p = i - (lo - m);
-                        const double ur = a.Bm[(int64_t)(w * W + c) * a.ldb + p];
-                        const double ui = a.Bm[(int64_t)(w * W + m + c) * a.ldb + p];
+                        const double ur = a.Bm[(int64_t)p * a.ldb + w * W + c];
+                        const double ui = a.Bm[(int64_t)p * a.ldb + w * W + m + c];
                         v -= q < m ? (sr * ur - si * ui) : (sr * ui + si * ur);
                     }
                 }

@@ -119,7 +119,7 @@ struct Layout {
     // blocked FP64 sweep (FP64 mode): carried columns, block transforms
     bool blocked = false;
     size_t zb = 0, bm = 0, m2 = 0, m2p = 0, m2q = 0;
-    int64_t blk_ldb = 0, blk_cols = 0;
+    int64_t blk_rows = 0, blk_cols = 0;
     size_t total = 0;
 };
 
@@ -147,9 +147,10 @@ bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
         if (!blk_geometry((int)m, &tr, &w)) return false;
         L->blocked = true;
         L->blk_cols = (w * s + 127) / 128 * 128;
-        L->blk_ldb = kBlkGroup * tr + m;
+        // rows of the block transforms, up to whole 16-row chunks
+        L->blk_rows = (kBlkGroup * tr + m + 15) / 16 * 16;
         L->zb = take(sizeof(double) * n * L->blk_cols);
-        L->bm = take(sizeof(double) * L->blk_ldb * L->blk_cols);
+        L->bm = take(sizeof(double) * L->blk_rows * L->blk_cols);
         L->m2 = take(sizeof(double) * (L->blk_cols / w) * w * w);
         L->m2p = take(sizeof(double) * (L->blk_cols / w) * w * w);
         L->m2q = take(sizeof(double) * (L->blk_cols / w) * w * w);
@@ -220,8 +221,10 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     double *Zb = at<double>(work, L.zb), *Bm = at<double>(work, L.bm), *M2 = at<double>(work, L.m2);
     double *M2p = at<double>(work, L.m2p), *M2q = at<double>(work, L.m2q);
     PhaseScope whole(h, PH_SWEEP, count, st);
-    // columns past 2m of each shift, and of the padding shifts, stay zero
-    hipError_t e = hipMemsetAsync(Bm, 0, sizeof(double) * L.blk_ldb * ncols, st);
+    // columns past 2m of each shift, those of the padding shifts and the
+    // rows past the bottom tile's K stay zero.  Bm is row-major with row
+    // stride ncols.
+    hipError_t e = hipMemsetAsync(Bm, 0, sizeof(double) * L.blk_rows * ncols, st);
     if (e != hipSuccess) return e;
     e = hipMemsetAsync(M2, 0, sizeof(double) * (ncols / w) * w * w, st);
     if (e != hipSuccess) return e;
@@ -246,17 +249,18 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     ta.Z = Zb;
     ta.ldz = n;
     ta.Bm = Bm;
-    ta.ldb = L.blk_ldb;
+    ta.ldb = ncols;
     ta.M2 = M2;
     ta.D = kBlkGroup;
     ZupdArgs za{};
     za.m = m;
+    za.n = n;
     za.ncols = (int)ncols;
     za.count = (int)count;
     za.H = h->H;
     za.ldh = h->ldh;
     za.Bm = Bm;
-    za.ldb = L.blk_ldb;
+    za.ldb = ncols;
     za.M2 = M2;
     za.Z = Zb;
     za.ldz = n;
@@ -303,7 +307,7 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
             za.r0 = lo - tr;   // the next tile's rows
             za.K = k * tr;
             za.has_zin = 1;
-            za.Bm = Bm + (kBlkGroup - k) * tr;
+            za.Bm = Bm + (int64_t)(kBlkGroup - k) * tr * ncols;
             za.M2 = m2cur;
         } else {
             za.r0 = 0;
@@ -632,7 +636,7 @@ int shs_reduce(int64_t n, int64_t m, int64_t p, const double *A, int64_t lda, co
     h->m = m;
     h->p = p;
     hipGetDevice(&h->device);
-    h->ldh = n;
+    h->ldh = (n + 15) / 16 * 16;   // 16-byte aligned pairs of rows in every column
     h->ldct = std::max<int64_t>(1, p);
     h->nrefl = m + std::max<int64_t>(0, n - m - 1);
     size_t acc = 0;
@@ -644,8 +648,8 @@ int shs_reduce(int64_t n, int64_t m, int64_t p, const double *A, int64_t lda, co
         e = dmalloc(&(ptr), (size_t)(cnt), &acc);      \
         if (e != hipSuccess) goto fail;                \
     } while (0)
-    ALLOC(h->H, n * n);
-    ALLOC(h->H32, n * n);
+    ALLOC(h->H, h->ldh * n);
+    ALLOC(h->H32, h->ldh * n);
     ALLOC(h->Bw, n * m);
     ALLOC(h->Rtop, m * m);
     ALLOC(h->rcolmax, m);
@@ -669,6 +673,8 @@ int shs_reduce(int64_t n, int64_t m, int64_t p, const double *A, int64_t lda, co
     e = hipEventRecord(e0, st);
     if (e != hipSuccess) goto fail;
 
+    e = hipMemsetAsync(h->H, 0, sizeof(double) * h->ldh * n, st);   // padding rows stay zero
+    if (e != hipSuccess) goto fail;
     e = hipMemcpy2DAsync(h->H, sizeof(double) * h->ldh, A, sizeof(double) * lda, sizeof(double) * n, n,
                          hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) goto fail;

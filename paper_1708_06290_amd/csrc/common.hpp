@@ -16,6 +16,11 @@ constexpr int kWave = 64;
 // The implicit last entry v_m of every reflector is 1.
 __host__ __device__ constexpr int slot_elems(int m, bool dense) { return 2 + 2 * m + (dense ? 2 * m : 0); }
 
+// Packed solutions of the residual GEMM: rows up to a whole chunk of 16,
+// row stride (in doubles) for `cols` complex columns up to a whole tile of 64.
+__host__ __device__ inline int64_t residual_pack_rows(int64_t n) { return (n + 15) / 16 * 16; }
+__host__ __device__ inline int64_t residual_pack_ld(int64_t cols) { return (cols + 63) / 64 * 128; }
+
 // Rows of the window a lane keeps in registers: the state of one row is
 // 2(m+1) values (+2m for a dense right-hand side); the budget keeps the
 // kernel near 200 VGPRs so that two waves fit on each SIMD.

@@ -46,7 +46,7 @@ namespace shs {
 // per-column scratch of m * s_total entries.
 hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const double *shifts, const double *X,
                    int64_t ldx, double *Res, unsigned long long *resmax, unsigned long long *xmax, double *eta,
-                   int32_t *status, int64_t s_total, hipStream_t st);
+                   int32_t *status, int64_t s_total, double *Xt, hipStream_t st);
 
 // G(:, j*m + c) = Ct X(:, j*m + c) for shifts 0 .. s-1.
 hipError_t g_eval(shs_handle *h, int64_t s, const double *X, int64_t ldx, double *G, int64_t ldg, hipStream_t st);

@@ -119,6 +119,7 @@ struct Layout {
     // blocked FP64 sweep (FP64 mode): carried columns, block transforms
     bool blocked = false;
     size_t zb = 0, bm = 0, m2 = 0, m2p = 0, m2q = 0;
+    size_t xt = 0;   // packed solutions for the residual
     int64_t blk_rows = 0, blk_cols = 0;
     size_t total = 0;
 };
@@ -142,6 +143,7 @@ bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
     L->xmax = take(sizeof(unsigned long long) * m * s);
     L->list = take(sizeof(int32_t) * s);
     L->status2 = take(sizeof(int32_t) * s);
+    L->xt = take(sizeof(double) * residual_pack_rows(n) * residual_pack_ld(m * s));
     if (mode == SHS_MODE_FP64) {
         int tr = 0, w = 0;
         if (!blk_geometry((int)m, &tr, &w)) return false;
@@ -387,7 +389,7 @@ namespace shs {
 // residual + eta for the listed shifts; Res optional.
 hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const double *shifts, const double *X,
                    int64_t ldx, double *Res, unsigned long long *resmax, unsigned long long *xmax, double *eta,
-                   int32_t *status, int64_t s_total, hipStream_t st)
+                   int32_t *status, int64_t s_total, double *Xt, hipStream_t st)
 {
     const int64_t n = h->n, m = h->m;
     PhaseScope ps(h, PH_RESIDUAL, s_list, st);
@@ -406,12 +408,19 @@ hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const do
     ra.shifts = shifts;
     ra.X = X;
     ra.ldx = ldx;
+    ra.Xt = Xt;
+    ra.ldxt = residual_pack_ld(s_list * m);
     ra.Res = Res;
     ra.ldr = n;
     ra.resmax = resmax;
     ra.xmax = xmax;
     if (s_list <= 0) return hipGetLastError();
-    hipLaunchKernelGGL(residual_mfma_kernel, dim3(cdiv(n, 128), cdiv(s_list * m, 64)), dim3(256), 0, st, ra);
+    // what the direct-to-LDS loads assume: 16-byte aligned pairs of rows
+    if (n < 2 || h->ldh & 1 || ((uintptr_t)h->H | (uintptr_t)Xt) & 15) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(residual_pack_kernel, dim3(cdiv(residual_pack_rows(n), 64), ra.ldxt / 128), dim3(256), 0, st,
+                       ra);
+    hipLaunchKernelGGL(residual_mfma_kernel, dim3(cdiv(n, 128), cdiv(s_list * m, 64)), dim3(256), kResidualLds, st,
+                       ra);
     hipLaunchKernelGGL(eta_kernel, dim3((unsigned)s_list), dim3(256), 0, st, (int)n, (int)m, (int)s_list, dlist,
                        shifts, (const double *)h->offrow, (const double *)h->diag, (const double *)h->rcolmax,
                        (const unsigned long long *)resmax, (const unsigned long long *)xmax, eta, status);
@@ -795,7 +804,7 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outp
         e = solve_fp64(h, s, nullptr, shifts, work, L, Xw, ldxw, status, st);
         if (e == hipSuccess && (outputs & SHS_OUT_ETA))
             e = certify(h, s, nullptr, shifts, Xw, ldxw, nullptr, at<unsigned long long>(work, L.resmax),
-                        at<unsigned long long>(work, L.xmax), eta, status, s, st);
+                        at<unsigned long long>(work, L.xmax), eta, status, s, at<double>(work, L.xt), st);
     } else {
         // ---- complex FP32 sweep, then FP64 iterative refinement -------------
         Geo g32s, g32d;
@@ -849,7 +858,7 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outp
             e = hipMemcpyAsync(dlist, active.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st);
             if (e != hipSuccess) break;
             e = certify(h, na, dlist, shifts, Xw, ldxw, Res, at<unsigned long long>(work, L.resmax),
-                        at<unsigned long long>(work, L.xmax), eta, nullptr, s, st);
+                        at<unsigned long long>(work, L.xmax), eta, nullptr, s, at<double>(work, L.xt), st);
             if (e != hipSuccess) break;
             e = hipMemcpyAsync(heta.data(), eta, sizeof(double) * s, hipMemcpyDeviceToHost, st);
             if (e != hipSuccess) break;
@@ -931,7 +940,7 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outp
             if (e == hipSuccess) e = solve_fp64(h, nf, dlist, shifts, work, L, Xw, ldxw, st2, st);
             if (e == hipSuccess)
                 e = certify(h, nf, dlist, shifts, Xw, ldxw, nullptr, at<unsigned long long>(work, L.resmax),
-                            at<unsigned long long>(work, L.xmax), eta, st2, s, st);
+                            at<unsigned long long>(work, L.xmax), eta, st2, s, at<double>(work, L.xt), st);
             if (e == hipSuccess)
                 hipLaunchKernelGGL(fill_status_kernel, dim3(cdiv(nf, 256)), dim3(256), 0, st, (int)nf,
                                    (const int32_t *)dlist, (const int32_t *)st2, status, SHS_STATUS_FALLBACK);

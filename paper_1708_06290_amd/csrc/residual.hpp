@@ -19,12 +19,14 @@ namespace shs {
 struct ResidualArgs {
     int n, m, count;            // count = number of listed shifts
     const int32_t *list;        // item -> shift id (nullptr = identity)
-    const double *H;            // n x n, ld ldh
+    const double *H;            // n x n, ld ldh (even, rows n .. ldh-1 zero)
     int64_t ldh;
     const double *Rtop;         // m x m, ld m
     const double *shifts;       // per shift id
     const double *X;            // n x (s m) complex, ld ldx
     int64_t ldx;
+    double *Xt;                 // packed copy of the listed columns (residual_pack_kernel)
+    int64_t ldxt;               // its row stride: 2 (count m rounded up to 64)
     double *Res;                // optional, n x (s m) complex, ld ldr (same column layout)
     int64_t ldr;
     unsigned long long *resmax; // per column (s m), max |Res| (bits of a non-negative double)
@@ -33,36 +35,82 @@ struct ResidualArgs {
 
 typedef double shs_dbl4 __attribute__((ext_vector_type(4)));
 
+// Xt(k, :) = the listed solutions, row k, k-major: complex column w (item
+// w / m, right-hand side w % m) is real column 16 (w / 8) + w % 8 (real part)
+// and 8 more (imaginary part), so every 16 real columns hold 8 whole complex
+// columns.  Rows n .. and columns past the list are zero.  A 64 x 64
+// complex tile goes through LDS: read along k (the columns of X), written
+// along the rows of Xt.
+__global__ __launch_bounds__(256) void residual_pack_kernel(ResidualArgs a)
+{
+    __shared__ double tr[64][65], ti[64][65];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int k0 = blockIdx.x * 64, w0 = blockIdx.y * 64;
+    const int ncols = a.count * a.m, m = a.m;
+    for (int q = wave; q < 64; q += 4) {
+        const int w = w0 + q, k = k0 + lane;
+        double xr = 0.0, xi = 0.0;
+        if (w < ncols && k < a.n) {
+            const int item = w / m, c = w % m;
+            const int sid = a.list ? a.list[item] : item;
+            const double *x = a.X + (((int64_t)sid * m + c) * a.ldx + k) * 2;
+            xr = x[0];
+            xi = x[1];
+        }
+        tr[lane][q] = xr;
+        ti[lane][q] = xi;
+    }
+    __syncthreads();
+    const int rows = (int)residual_pack_rows(a.n);
+    for (int e = tid; e < 64 * 128; e += 256) {
+        const int kk = e / 128, j = e % 128, k = k0 + kk;
+        if (k >= rows) break;
+        const int q = (j / 16) * 8 + j % 8;   // complex column in the tile
+        const double v = (j % 16) < 8 ? tr[kk][q] : ti[kk][q];
+        a.Xt[(int64_t)k * a.ldxt + 2 * w0 + j] = v;
+    }
+}
+
+// LDS of residual_mfma_kernel (dynamic): two stages of a 16-row chunk of
+// H^T (128 rows of H) and of Xt (128 real columns).
+constexpr int kResidualLds = 2 * 2 * 16 * 128 * (int)sizeof(double);
+
 // The residual on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  A
-// workgroup of 4 waves computes 128 rows x 64 complex columns; wave (wr, wc)
-// owns rows wr*64 .. +63 and complex columns wc*32 .. +31 as 4 x 4 MFMA
-// tiles of 16 x 16.  In LDS the X tile keeps, for each group of 16 complex
-// columns, the 16 real parts followed by the 16 imaginary parts, so N-tiles
-// 2g and 2g+1 of a wave hold the real and imaginary parts of the same 16
-// complex columns and every lane ends with whole complex results.  MFMA
-// operand layout: lane l holds A(l%16, l/16) and B(l/16, l%16); result
-// register r of lane l is D(4 r + l/16, l%16).
+// workgroup of 4 waves computes 128 rows x 64 complex columns (128 real
+// columns of Xt); wave (wr, wc) owns rows wr*64 .. +63 and real columns
+// wc*64 .. +63 as 4 x 4 MFMA tiles of 16 x 16.  MFMA operand layout: lane l
+// holds A(l%16, l/16) and B(l/16, l%16); result register r of lane l is
+// D(4 r + l/16, l%16).  Each 16-column tile holds the real parts of 8
+// complex columns and then their imaginary parts, so lanes l and l ^ 8 hold
+// the two parts of one complex result.
 //
-// K streams through double-buffered LDS in chunks of 16, stored [row][k]
-// with one column of padding (conflict-free fragment reads and stores).
-// The chunks k0 .. k0+15 that cover the workgroup's own rows also carry
-// X(i, :) for those rows, so sigma X and max |x| are taken from LDS there:
-// the epilogue makes no dependent loads.
+// K streams through two LDS stages that the memory system fills directly
+// (global_load_lds_dwordx4, two consecutive doubles of one row of H^T or of
+// Xt per lane), k-major on both sides as H and Xt lie in memory; the
+// fragment reads of 16 consecutive rows or columns are free of bank
+// conflicts.  Rows of H at or past ldh - 1 read row ldh - 2 (never stored);
+// chunk rows past n - 1 read column n - 1 of H against zero rows of Xt.
+// H is m-Hessenberg, so for a block of rows [i0, i0 + 128) only columns
+// k >= i0 - m contribute: the k loop stops there.  It runs downwards from
+// the last row of H, so the row tiles of one column tile (consecutive
+// workgroups, spread over the XCDs, which then get long and short K ranges
+// alike) read the same rows of Xt at the same time.  The chunks that cover
+// the workgroup's own rows also carry X(i, :) for those rows, so sigma X and
+// max |x| are taken from LDS there: the epilogue makes no dependent loads.
 __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
 {
-    constexpr int BM = 128, BNC = 64, BK = 16, PK = BK + 1;
-    __shared__ double Hs[2][BM][PK];
-    __shared__ double Xs[2][2 * BNC][PK];
+    constexpr int BM = 128, BN = 128, BK = 16;
+    extern __shared__ double res_smem[];
+    auto Hs = reinterpret_cast<double (*)[BK][BM]>(res_smem);
+    auto Xs = reinterpret_cast<double (*)[BK][BN]>(res_smem + 2 * BK * BM);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int ncols = a.count * a.m;
     const int n = a.n, m = a.m;
-    // The K loop runs downwards from the last row of H: row tiles of one
-    // column tile (consecutive workgroups, spread over the XCDs, so each XCD
-    // gets long and short K ranges alike) then read the same rows of X at the
-    // same time, since all their K ranges end at n.
     const int i0 = blockIdx.x * BM;
-    const int w0 = blockIdx.y * BNC;
+    const int w0 = blockIdx.y * (BN / 2);   // first complex column of the tile
+    const int q = lane % 16;
+    const bool re_lane = q < 8;
 
     shs_dbl4 acc[4][4];
 #pragma unroll
@@ -70,54 +118,29 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = shs_dbl4{0.0, 0.0, 0.0, 0.0};
 
-    // loads of this thread: H rows i0 + tid%128, k = k0 + tid/128 + 2e (e < 8);
-    // X row k0 + tid%16 of complex tile columns tid/16 + 16e (e < 4)
-    const double *xcol[4];
-    bool xok[4];
+    // this lane's complex column in each N-tile, and its shift
+    double sgr[4], sgi[4], mx[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int w = w0 + tid / 16 + 16 * e;
-        xok[e] = w < ncols;
-        const int ww = xok[e] ? w : 0;
-        const int item = ww / m, c = ww % m;
-        const int sid = a.list ? a.list[item] : item;
-        xcol[e] = a.X + ((int64_t)sid * m + c) * a.ldx * 2;
-    }
-    // this lane's two complex columns (g = 0, 1) and their shifts
-    double sgr[2], sgi[2], mx[2] = {0.0, 0.0};
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-        const int w = w0 + wc * 32 + g * 16 + lane % 16;
+    for (int nt = 0; nt < 4; ++nt) {
+        const int w = w0 + wc * 32 + nt * 8 + q % 8;
         const int item = (w < ncols ? w : 0) / m;
         const int sid = a.list ? a.list[item] : item;
-        sgr[g] = a.shifts[2 * sid];
-        sgi[g] = a.shifts[2 * sid + 1];
+        sgr[nt] = a.shifts[2 * sid];
+        sgi[nt] = a.shifts[2 * sid + 1];
+        mx[nt] = 0.0;
     }
-    const int hr = tid % BM, hk = tid / BM;
-    const int xk = tid % BK, xc = tid / BK;
-    double hreg[8], xre[4], xim[4];
-    auto gload = [&](int k0) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int i = i0 + hr, k = k0 + hk + 2 * e;
-            hreg[e] = (i < n && k < n) ? a.H[(int64_t)k * a.ldh + i] : 0.0;
-        }
+    // wave w moves rows 4w .. 4w+3 of each chunk of both operands
+    const double *pa = a.H + min((int64_t)(i0 + 2 * lane), a.ldh - 2);
+    const double *pb = a.Xt + 2 * w0 + 2 * lane;
+    auto issue = [&](int b, int k0) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int k = k0 + xk;
-            const bool ok = xok[e] && k < n;
-            xre[e] = ok ? xcol[e][2 * (int64_t)k] : 0.0;
-            xim[e] = ok ? xcol[e][2 * (int64_t)k + 1] : 0.0;
-        }
-    };
-    auto lstore = [&](int b) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) Hs[b][hr][hk + 2 * e] = hreg[e];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int cc = xc + 16 * e, g = cc / 16, j = cc % 16;
-            Xs[b][32 * g + j][xk] = xre[e];
-            Xs[b][32 * g + 16 + j][xk] = xim[e];
+            const int k = 4 * wave + e;
+            const int col = min(k0 + k, n - 1);
+            __builtin_amdgcn_global_load_lds((const void *)(pa + (int64_t)col * a.ldh),
+                                             (__attribute__((address_space(3))) void *)&Hs[b][k][0], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(pb + (int64_t)(k0 + k) * a.ldxt),
+                                             (__attribute__((address_space(3))) void *)&Xs[b][k][0], 16, 0, 0);
         }
     };
 
@@ -125,85 +148,86 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
     if (kstart < 0) kstart = 0;
     kstart = (kstart / BK) * BK;
     const int ktop = ((n - 1) / BK) * BK;   // chunk holding the last row of H
-    gload(ktop);
-    lstore(0);
-    if (ktop - BK >= kstart) gload(ktop - BK);
+    issue(0, ktop);
+    __builtin_amdgcn_s_waitcnt(0x0070);     // vmcnt(0) lgkmcnt(0)
     __syncthreads();
-    int buf = 0;
+    int b = 0;
     for (int k0 = ktop; k0 >= kstart; k0 -= BK) {
+        double af[4][4], bf[4][4];
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            double af[4], bf[4];
+        for (int s = 0; s < 4; ++s) {
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) af[mt] = Hs[buf][wr * 64 + mt * 16 + lane % 16][kk + lane / 16];
+            for (int mt = 0; mt < 4; ++mt) af[s][mt] = Hs[b][4 * s + lane / 16][wr * 64 + mt * 16 + lane % 16];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) bf[nt] = Xs[buf][wc * 64 + nt * 16 + lane % 16][kk + lane / 16];
+            for (int nt = 0; nt < 4; ++nt) bf[s][nt] = Xs[b][4 * s + lane / 16][wc * 64 + nt * 16 + lane % 16];
+        }
+        // the other stage was last read before the previous barrier
+        if (k0 - BK >= kstart) issue(b ^ 1, k0 - BK);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mt], bf[nt], acc[mt][nt], 0, 0, 0);
-        }
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s][mt], bf[s][nt], acc[mt][nt], 0, 0, 0);
         // the chunk holds X(i, :) for the 16 rows i = k0 .. k0+15: block mt of
         // the waves with wr = (k0 - i0) / 64 (uniform per wave)
         const int d = k0 - i0;
         if (d >= 0 && d < BM && (d >> 6) == wr) {
-            const int mt = (d & 63) >> 4;
+            const int mtd = (d & 63) >> 4;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (q != mt) continue;
+            for (int mt = 0; mt < 4; ++mt) {
+                if (mt != mtd) continue;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int kr = 4 * r + lane / 16;   // row k0 + kr
 #pragma unroll
-                    for (int g = 0; g < 2; ++g) {
-                        const double xr = Xs[buf][wc * 64 + 32 * g + lane % 16][kr];
-                        const double xi = Xs[buf][wc * 64 + 32 * g + 16 + lane % 16][kr];
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int jj = wc * 64 + nt * 16 + q % 8;
+                        const double xr = Xs[b][kr][jj], xi = Xs[b][kr][jj + 8];
                         // H X - sigma X
-                        acc[q][2 * g][r] -= sgr[g] * xr - sgi[g] * xi;
-                        acc[q][2 * g + 1][r] -= sgr[g] * xi + sgi[g] * xr;
+                        acc[mt][nt][r] -= re_lane ? sgr[nt] * xr - sgi[nt] * xi : sgr[nt] * xi + sgi[nt] * xr;
                         const double ax = hypot(xr, xi);
-                        mx[g] = (ax > mx[g] || ax != ax) ? ax : mx[g];
+                        mx[nt] = (ax > mx[nt] || ax != ax) ? ax : mx[nt];
                     }
                 }
             }
         }
-        if (k0 - BK >= kstart) {
-            // the other buffer was last read before the previous barrier
-            lstore(buf ^ 1);
-            if (k0 - 2 * BK >= kstart) gload(k0 - 2 * BK);
-        }
+        // keep the wait for the next chunk behind this chunk's products
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0x0070);
         __syncthreads();
-        buf ^= 1;
+        b ^= 1;
     }
 
-    // epilogue: Res = R - (H X - sigma X) and column maxima
+    // epilogue: Res = R - (H X - sigma X) and column maxima; the real-part
+    // lanes (q < 8) take the pair
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
-        const int w = w0 + wc * 32 + g * 16 + lane % 16;
-        double mr = 0.0, mxg = mx[g];
-        if (w < ncols) {
-            const int item = w / m, c = w % m;
-            const int sid = a.list ? a.list[item] : item;
-            const int64_t col = (int64_t)sid * m + c;
+    for (int nt = 0; nt < 4; ++nt) {
+        const int w = w0 + wc * 32 + nt * 8 + q % 8;
+        const bool ok = w < ncols;
+        const int item = (ok ? w : 0) / m, c = (ok ? w : 0) % m;
+        const int sid = a.list ? a.list[item] : item;
+        const int64_t col = (int64_t)sid * m + c;
+        double mr = 0.0, mxg = mx[nt];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
+        for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = i0 + wr * 64 + mt * 16 + 4 * r + lane / 16;
-                    if (i < n) {
-                        const double rr = ((i < m) ? a.Rtop[c * m + i] : 0.0) - acc[mt][2 * g][r];
-                        const double ri = -acc[mt][2 * g + 1][r];
-                        if (a.Res) {
-                            double *pr = a.Res + (col * a.ldr + i) * 2;
-                            pr[0] = rr;
-                            pr[1] = ri;
-                        }
-                        const double ar = hypot(rr, ri);
-                        mr = (ar > mr || ar != ar) ? ar : mr;
+            for (int r = 0; r < 4; ++r) {
+                const double v = acc[mt][nt][r], o = __shfl_xor(v, 8);
+                const int i = i0 + wr * 64 + mt * 16 + 4 * r + lane / 16;
+                if (ok && re_lane && i < n) {
+                    const double rr = ((i < m) ? a.Rtop[c * m + i] : 0.0) - v;
+                    const double ri = -o;
+                    if (a.Res) {
+                        double *pr = a.Res + (col * a.ldr + i) * 2;
+                        pr[0] = rr;
+                        pr[1] = ri;
                     }
+                    const double ar = hypot(rr, ri);
+                    mr = (ar > mr || ar != ar) ? ar : mr;
                 }
-        }
+            }
         // lanes l, l+16, l+32, l+48 hold the same column
 #pragma unroll
         for (int off = 16; off < 64; off <<= 1) {
@@ -211,10 +235,7 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
             mr = (orr > mr || orr != orr) ? orr : mr;
             mxg = (oxx > mxg || oxx != oxx) ? oxx : mxg;
         }
-        if (lane < 16 && w < ncols) {
-            const int item = w / m, c = w % m;
-            const int sid = a.list ? a.list[item] : item;
-            const int64_t col = (int64_t)sid * m + c;
+        if (lane < 8 && ok) {
             if (mr != mr) mr = __longlong_as_double(0x7ff8000000000000LL);
             if (mxg != mxg) mxg = __longlong_as_double(0x7ff8000000000000LL);
             atomic_max_nonneg(a.resmax + col, mr);

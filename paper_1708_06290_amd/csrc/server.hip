@@ -58,9 +58,10 @@ size_t fp64_item_bytes(const shs_handle *h, int64_t s)
     const size_t refl = sizeof(double) * (size_t)g.refl_stride((int)h->n) * (size_t)s;
     const size_t y = sizeof(double) * 2 * (size_t)(h->m * h->m) * (size_t)s;
     const size_t xw = sizeof(double) * 2 * (size_t)(h->n * h->m) * (size_t)s;   // X when not requested
+    const size_t xt = sizeof(double) * (size_t)residual_pack_rows(h->n) * (size_t)residual_pack_ld(h->m * s);
     const size_t misc = 2 * sizeof(double) * (size_t)s + 2 * sizeof(unsigned long long) * (size_t)(h->m * s) +
-                        sizeof(ServeItem) * (size_t)s + 4 * 256;
-    return refl + y + xw + misc;
+                        sizeof(ServeItem) * (size_t)s + 5 * 256;
+    return refl + y + xw + xt + misc;
 }
 
 inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -97,7 +98,7 @@ int shs_server::run_fp64_batch(std::vector<std::shared_ptr<Request>> &batch, hip
 {
     // workspace layout: per request its scratch, then the item list and counter
     size_t total = 0;
-    struct Off { size_t refl, y, xw, shifts, resmax, xmax; };
+    struct Off { size_t refl, y, xw, shifts, resmax, xmax, xt; };
     std::vector<Off> offs(batch.size());
     int64_t nitems = 0;
     for (size_t b = 0; b < batch.size(); ++b) {
@@ -112,6 +113,7 @@ int shs_server::run_fp64_batch(std::vector<std::shared_ptr<Request>> &batch, hip
         offs[b].shifts = take(sizeof(double) * 2 * r.s);
         offs[b].resmax = take(sizeof(unsigned long long) * (size_t)(h->m * r.s));
         offs[b].xmax = take(sizeof(unsigned long long) * (size_t)(h->m * r.s));
+        offs[b].xt = take(sizeof(double) * (size_t)residual_pack_rows(h->n) * (size_t)residual_pack_ld(h->m * r.s));
         nitems += r.s;
     }
     const size_t items_off = total;
@@ -170,7 +172,7 @@ int shs_server::run_fp64_batch(std::vector<std::shared_ptr<Request>> &batch, hip
         if (e == hipSuccess && (r.outputs & SHS_OUT_ETA))
             e = certify(h, r.s, nullptr, (const double *)(work + offs[b].shifts), X, ldx, nullptr,
                         (unsigned long long *)(work + offs[b].resmax), (unsigned long long *)(work + offs[b].xmax),
-                        r.eta, r.status, r.s, st);
+                        r.eta, r.status, r.s, (double *)(work + offs[b].xt), st);
     }
     hipError_t e2 = hipFreeAsync(work, st);
     if (e == hipSuccess) e = e2;

@@ -114,20 +114,18 @@ __device__ __forceinline__ const T *refl_slot(const T *rf, int k, int tt, int64_
     return rf + (int64_t)t * tstride + (int64_t)(k - t * tt) * S;
 }
 
-// Fresh column `col` of H for this lane's rows (0 if col < 0).  Rows past n
-// (the ragged bottom tile) read row n-1 instead: they are never pivots and
-// never feed another row, so their values do not matter, and the loads stay
-// free of per-lane branches.
+// Fresh column `col` of H for this lane's rows.  Rows past n (the ragged
+// bottom tile) read row n-1 instead: they are never pivots and never feed
+// another row, so their values do not matter, and the loads stay free of
+// per-lane branches.  A negative col reads column 0, and the consumer
+// (apply_step) takes zeros instead; the loads are so issued on every step,
+// and with no branch around them the waits for them count exactly the
+// memory operations issued since.
 template <typename T, int R>
 __device__ __forceinline__ void load_fresh(const T *H, int64_t ldh, int n, int lo, int lane, int col,
                                            T (&fr)[R])
 {
-    if (col < 0) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) fr[r] = T(0);
-        return;
-    }
-    const T *cp = H + (int64_t)col * ldh;
+    const T *cp = H + (int64_t)(col < 0 ? 0 : col) * ldh;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = lo + r * kWave + lane;
@@ -218,12 +216,13 @@ __device__ __forceinline__ void apply_step(T (&wr)[R][M + 1], T (&wi)[R][M + 1],
             }
             if (r == 0) { d0r = xr; d0i = xi; }
         }
+        const T f = fcol >= 0 ? fr[r] : T(0);   // columns left of 0 are zero
         if (fcol >= lo && fcol < lo + R * kWave) {   // uniform: a diagonal entry enters
             const bool dg = (lo + r * kWave + lane) == fcol;
-            wr[r][pm] = dg ? fr[r] - sgr : fr[r];
+            wr[r][pm] = dg ? f - sgr : f;
             wi[r][pm] = dg ? -sgi : T(0);
         } else {
-            wr[r][pm] = fr[r];
+            wr[r][pm] = f;
             wi[r][pm] = T(0);
         }
     }
@@ -329,12 +328,17 @@ __device__ __forceinline__ void tri_step(int k, int k_lo, int n, int lo, int lan
         yr[0] = T(0);
         yi[0] = T(0);
     }
-    if (lane == 0) {
+    {
+        // every lane stores the same (uniform) values: no branch around the
+        // stores, so the waits for the fresh-column loads stay exact
         T *p = const_cast<T *>(refl_slot<T>(rf, k, TT, tstride, S));
         p[0] = tau;
         p[1] = T(0);
 #pragma unroll
         for (int j = 0; j < M; ++j) { p[2 + 2 * j] = vr[j]; p[3 + 2 * j] = vi[j]; }
+    }
+    if (lane == 0) {
+        T *p = const_cast<T *>(refl_slot<T>(rf, k, TT, tstride, S));
         if constexpr (DENSE) {
 #pragma unroll
             for (int c = 0; c < M; ++c) {

@@ -138,6 +138,11 @@ __device__ __forceinline__ void load_fresh(const T *H, int64_t ldh, int n, int l
 // w P = conj(beta') e_m^T.  With u = x - beta' e_m scaled to u_m = 1:
 // v_j = conj(w_j) / u_m, tau = 2 |u_m|^2 / ||u||^2.  A row that is already
 // [0 ... 0 w_m] gives tau = 0 (P = I) and beta = w_m.
+//
+// With a = |alpha|, phase ph = alpha / a (1 when a = 0), nu = ||x|| and
+// u_m = ph (a + nu): ||u||^2 = 2 nu (a + nu), so tau = (a + nu) / nu, and
+// 1 / u_m = conj(ph) / (a + nu) = conj(alpha) / (a (a + nu)).  Two
+// divisions per reflector.
 template <typename T, int M>
 __device__ __forceinline__ void make_refl(const T (&pr)[M + 1], const T (&pi)[M + 1], T (&vr)[M], T (&vi)[M],
                                           T &tau, T &br, T &bi)
@@ -146,31 +151,31 @@ __device__ __forceinline__ void make_refl(const T (&pr)[M + 1], const T (&pi)[M 
 #pragma unroll
     for (int j = 0; j < M; ++j) sig2 = fma(pr[j], pr[j], fma(pi[j], pi[j], sig2));
     const T ar = pr[M], ai = -pi[M];
-    if (sig2 == T(0)) {
-        tau = T(0);
-#pragma unroll
-        for (int j = 0; j < M; ++j) { vr[j] = T(0); vi[j] = T(0); }
-        br = pr[M];
-        bi = pi[M];
-        return;
-    }
+    // no branch for the already-reduced row (sig2 = 0): there x_j = 0, so v
+    // comes out zero as long as the scale below is finite, and tau and beta
+    // are selected
+    const bool z = sig2 == T(0);
     const T aa = dsqrt<T>(fma(ar, ar, ai * ai));
     const T nu = dsqrt<T>(fma(aa, aa, sig2));
-    T phr = T(1), phi = T(0);
-    if (aa > T(0)) { phr = ar / aa; phi = ai / aa; }
     const T um = aa + nu;                // |u_m|
-    const T umr = phr * um, umi = phi * um;
-    const T inv = T(1) / (um * um);
+    const bool ph = aa > T(0);
+    // cr - i ci = conj(u_m) / |u_m|^2 = conj(ph) / um (zero for a zero row)
+    const T d = ph ? aa * um : um;
+    const T q = d > T(0) ? T(1) / d : T(0);
+    const T cr = (ph ? ar : T(1)) * q, ci = (ph ? ai : T(0)) * q;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         // conj(w_j) * conj(u_m) / |u_m|^2
         const T xr = pr[j], xi = -pi[j];
-        vr[j] = (xr * umr + xi * umi) * inv;
-        vi[j] = (xi * umr - xr * umi) * inv;
+        vr[j] = fma(xr, cr, xi * ci);
+        vi[j] = fma(xi, cr, -(xr * ci));
     }
-    tau = (T(2) * um * um) / (sig2 + um * um);
-    br = -phr * nu;
-    bi = phi * nu;
+    tau = z ? T(0) : um / nu;
+    // beta = -ph nu (as conj(beta') e_m^T = w P), ph = (cr + i ci) um;
+    // w_m itself when P = I
+    const T s = nu * um;
+    br = z ? pr[M] : -cr * s;
+    bi = z ? pi[M] : ci * s;
 }
 
 // Apply P_k to row slots [0, RA) at phase Q = k mod (m+1), then slide: the

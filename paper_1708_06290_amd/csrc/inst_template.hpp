@@ -25,15 +25,21 @@ struct Inst {
         else
             hipLaunchKernelGGL((sweep_kernel<REAL_T, MM, false>), dim3(a.count), dim3(kWave), 0, st, a);
     }
-    static void qstar(bool dense_in, const QstarArgs<REAL_T> &a, hipStream_t st)
+    static bool qstar(bool dense_in, const QstarArgs<REAL_T> &a, hipStream_t st)
     {
         if (dense_in) {
             constexpr int spw = kWave / MM;
             const int blocks = (a.count + spw - 1) / spw;
             hipLaunchKernelGGL((qstar_kernel<REAL_T, MM, true>), dim3(blocks), dim3(kWave), 0, st, a);
         } else if (a.count > 0) {
-            hipLaunchKernelGGL((qstar_wave_kernel<REAL_T, MM>), dim3(a.count), dim3(kWave), 0, st, a);
+            // the kernel reads the structured store's slots (and needs a tile
+            // of at least one phase group)
+            if (a.slot != slot_elems(MM, false) || a.tile_rows < MM + 1) return false;
+            const int spw = qstar_spw(a.count, MM);
+            hipLaunchKernelGGL((qstar_wave_kernel<REAL_T, MM>), dim3((a.count + spw - 1) / spw), dim3(kWave), 0, st,
+                               a, spw);
         }
+        return true;
     }
 };
 
@@ -57,7 +63,7 @@ bool SHS_CAT3(launch_sweep_, SUFFIX, PART)(int m, bool dense, const SweepArgs<RE
 bool SHS_CAT3(launch_qstar_, SUFFIX, PART)(int m, bool dense_in, const QstarArgs<REAL_T> &a, hipStream_t st)
 {
     bool ok = false;
-    SHS_DISPATCH_M(m, if constexpr (MM >= M_FIRST && MM <= M_LAST) { Inst<MM>::qstar(dense_in, a, st); ok = true; });
+    SHS_DISPATCH_M(m, if constexpr (MM >= M_FIRST && MM <= M_LAST) { ok = Inst<MM>::qstar(dense_in, a, st); });
     return ok;
 }
 

@@ -153,42 +153,58 @@ __global__ __launch_bounds__(64) void qstar_kernel(QstarArgs<T> a)
     qstar_body<T, M, DENSE_IN>(a.n, active, c, rf, a.tile_rows, a.tile_stride, a.slot, Y, X, a.accumulate, sc);
 }
 
-// Structured right-hand side ([Y; 0], Y m x m), one wavefront per shift:
-// lanes c < m own column c as above, while the whole wave stages the
+// Structured right-hand side ([Y; 0], Y m x m), spw shifts per wavefront
+// (spw a power of two, spw m <= 64): lanes q m + c, c < m, own column c of
+// the wave's shift q as above, while the whole wave stages the shifts'
 // reflectors through LDS in chunks of whole phase groups (coalesced loads,
 // the next chunk in flight while the current one is used), so the serial
-// chain of n steps does not wait on memory.  The inner product v^* y is
-// summed in two interleaved partial sums to halve its dependence chain.
+// chain of n steps does not wait on memory.  spw is chosen by the caller to
+// give about one wave per SIMD.  The inner product v^* y is summed in two
+// interleaved partial sums to halve its dependence chain.
+constexpr int kQstarLds = 1536;   // LDS elements of one chunk (all shifts)
+
 template <typename T, int M>
-__global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a)
+__global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a, int spw)
 {
     constexpr int NP = M + 1;
-    constexpr int CE = 1536;                    // LDS elements per chunk
+    constexpr int S = slot_elems(M, false);
+    constexpr int CE = kQstarLds;
     constexpr int PL = CE / kWave;
-    static_assert(CE % kWave == 0 && CE >= slot_elems(M, true) * NP, "chunk");
+    static_assert(CE % kWave == 0 && CE >= S * NP + 1, "chunk");
     __shared__ T lds_ch[CE];
-    const int item = blockIdx.x;
-    if (item >= a.count || a.n < 1) return;
     const int lane = threadIdx.x;
-    const int c = lane < M ? lane : 0;
-    const int n = a.n, S = a.slot;
-    const int CS = NP * ((CE / S) / NP);        // steps per chunk, >= m+1
-    const int ce_elems = CS * S;
-    const int sid = a.list ? a.list[item] : item;
-    const T *rf = a.refl + (int64_t)sid * a.refl_stride;
+    const int n = a.n;
+    // steps per chunk (at most a tile, so a chunk spans two tiles at most)
+    // and LDS stride per shift (odd: the shifts' reads fall in different banks)
+    const int CS = NP * (min((CE / spw - 1) / S, a.tile_rows) / NP);
+    const int RS = CS * S + 1;
+    const int gl = kWave / spw;                  // lanes loading one shift's chunk
+    const int lq = lane / gl, ll = lane % gl;    // loader: shift, lane within
+    const int q = lane / M, c = lane % M;        // compute: shift, column
+    const int item = blockIdx.x * spw + q;
+    const bool active = q < spw && item < a.count;
+    const int litem = blockIdx.x * spw + lq;
+    const bool lact = litem < a.count;
+    const int sid = active ? (a.list ? a.list[item] : item) : 0;
+    const int lsid = lact ? (a.list ? a.list[litem] : litem) : 0;
+    const T *rf = a.refl + (int64_t)lsid * a.refl_stride;
     const T *Y = a.Y + (int64_t)sid * a.y_stride;
     double *X = a.X + ((int64_t)sid * M + c) * a.ldx * 2;
     const double sc = (a.accumulate && a.scale) ? a.scale[sid] : 1.0;
+    const int ce_elems = CS * S;   // elements of one shift's chunk
+    const int tt = a.tile_rows;
     T pre[PL];
-    // slots past n-1 are read from slot n-1 and never used
+    // steps past n-1 are read from step n-1 and never used
     auto fetch = [&](int cb) {
+        const int t0 = cb / tt, kb = (t0 + 1) * tt;   // the chunk spans tiles t0, t0 + 1
 #pragma unroll
         for (int e = 0; e < PL; ++e) {
-            const int idx0 = e * kWave + lane;
+            const int idx0 = e * gl + ll;
             const int idx = idx0 < ce_elems ? idx0 : ce_elems - 1;
             const int ks = idx / S, el = idx - ks * S;
             const int k = min(cb + ks, n - 1);
-            pre[e] = refl_slot<T>(rf, k, a.tile_rows, a.tile_stride, S)[el];
+            const int t = k < kb ? t0 : t0 + 1;
+            pre[e] = rf[(int64_t)t * a.tile_stride + (int64_t)(k - t * tt) * S + el];
         }
     };
     double yr[NP], yi[NP];
@@ -203,12 +219,13 @@ __global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a)
         __syncthreads();            // previous chunk fully read
 #pragma unroll
         for (int e = 0; e < PL; ++e) {
-            const int idx = e * kWave + lane;
-            if (idx < ce_elems) lds_ch[idx] = pre[e];
+            const int idx = e * gl + ll;
+            if (idx < ce_elems) lds_ch[lq * RS + idx] = pre[e];
         }
         __syncthreads();
         if (cb + CS < n) fetch(cb + CS);
-        if (lane < M) {
+        if (active) {
+            const T *base = lds_ch + q * RS;
             const int ce = min(k_last + 1, cb + CS);
             for (int kg = cb; kg < ce; kg += NP) {
                 static_for<NP>([&](auto qc) {
@@ -216,7 +233,7 @@ __global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a)
                     const int k = kg + Q;
                     if (k < ce) {
                         if (k < n) {
-                            const T *pv = lds_ch + (k - cb) * S;
+                            const T *pv = base + (k - cb) * S;
                             const double tau = (double)pv[0];
                             double vr[M], vi[M];
 #pragma unroll
@@ -269,6 +286,17 @@ __global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a)
             }
         }
     }
+}
+
+// Shifts per wave for count shifts at m: about one wave per SIMD (1024 of
+// them), as many shifts as the lanes and a chunk of at least one phase
+// group per shift allow.
+inline int qstar_spw(int64_t count, int m)
+{
+    const int S = slot_elems(m, false);
+    int spw = 1;
+    while (spw * 2 * m <= kWave && (kQstarLds / (spw * 2) - 1) / S >= m + 1 && count > (int64_t)spw * 1024) spw *= 2;
+    return spw;
 }
 
 }  // namespace shs

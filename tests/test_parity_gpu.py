@@ -260,3 +260,32 @@ def test_nonfinite_shift_stays_confined():
     Xa, Xb = ra.X.cpu().numpy(), rb.X.cpu().numpy()
     keep = np.concatenate([np.arange(0, 3 * m), np.arange(4 * m, 8 * m)])
     assert np.array_equal(Xa, Xb[:, keep])
+
+
+# Enough shifts that the Q* pass packs several shifts into each wavefront
+# (m = 2: 8 per wave past 4096 shifts; m = 4: 4 per wave past 2048; the
+# mixed form runs the same pass in FP32): a subset solved alone agrees
+# bitwise, and sampled shifts agree with the oracle.
+@pytest.mark.parametrize("n,m,s,mode", [(300, 2, 4500, "fp64"), (260, 4, 2100, "fp64"), (260, 4, 2100, "mixed")])
+def test_many_shifts_per_wave(n, m, s, mode):
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    md = ss.SHS_MODE_FP64 if mode == "fp64" else ss.SHS_MODE_FP32_REFINE
+    print(f"case n={n} m={m} s={s} {mode}", flush=True)
+    A, B, C = workloads.system(n, m, 1, 47)
+    rng = np.random.default_rng(47)
+    shifts = (rng.uniform(-1.0, 1.0, s) + 1j * rng.uniform(0.5, 20.0, s)) * 10.0
+    sysm = ss.System(A, B, C)
+    res = sysm.solve(shifts, mode=md)
+    torch.cuda.synchronize()
+    assert (res.eta.cpu().numpy() <= ETA_TOL).all()
+    idx = np.unique(np.linspace(0, s - 1, 24).round().astype(int))
+    sub = sysm.solve(shifts[idx], mode=md)
+    torch.cuda.synchronize()
+    X = res.X.cpu().numpy()
+    cols = np.concatenate([np.arange(j * m, (j + 1) * m) for j in idx])
+    if mode == "fp64":
+        assert np.array_equal(X[:, cols], sub.X.cpu().numpy())
+    H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
+    Xo, _, _, _ = oracle.solve(H, R, Ct, shifts[idx])
+    _check_against(X[:, cols], Xo, m)

@@ -172,6 +172,7 @@ __global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a, int spw)
     constexpr int PL = CE / kWave;
     static_assert(CE % kWave == 0 && CE >= S * NP + 1, "chunk");
     __shared__ T lds_ch[CE];
+    __shared__ T lds_y[kWave * 2 * M];   // every shift's Y (spw m <= 64)
     const int lane = threadIdx.x;
     const int n = a.n;
     // steps per chunk (at most a tile, so a chunk spans two tiles at most)
@@ -188,7 +189,6 @@ __global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a, int spw)
     const int sid = active ? (a.list ? a.list[item] : item) : 0;
     const int lsid = lact ? (a.list ? a.list[litem] : litem) : 0;
     const T *rf = a.refl + (int64_t)lsid * a.refl_stride;
-    const T *Y = a.Y + (int64_t)sid * a.y_stride;
     double *X = a.X + ((int64_t)sid * M + c) * a.ldx * 2;
     const double sc = (a.accumulate && a.scale) ? a.scale[sid] : 1.0;
     const int ce_elems = CS * S;   // elements of one shift's chunk
@@ -207,12 +207,21 @@ __global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a, int spw)
             pre[e] = rf[(int64_t)t * a.tile_stride + (int64_t)(k - t * tt) * S + el];
         }
     };
+    // Y of every shift into LDS, so the rows entering in the first m steps
+    // are no memory loads (a wait for one would also wait for the stores of
+    // X and the chunk in flight)
+    {
+        const T *ys = a.Y + (int64_t)lsid * a.y_stride;
+        for (int e = ll; e < 2 * M * M; e += gl) lds_y[lq * 2 * M * M + e] = ys[e];
+    }
+    __syncthreads();
+    const T *yl = lds_y + q * 2 * M * M + 2 * c * M;   // Y(:, c) of this lane's shift
     double yr[NP], yi[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) { yr[j] = 0.0; yi[j] = 0.0; }
     // phase 0: logical j in slot j; row 0 is logical m
-    yr[M] = (double)Y[2 * (c * M)];
-    yi[M] = (double)Y[2 * (c * M) + 1];
+    yr[M] = (double)yl[0];
+    yi[M] = (double)yl[1];
     const int k_last = n - 1 + M;   // steps k >= n only flush the window
     fetch(0);
     for (int cb = 0; cb <= k_last; cb += CS) {
@@ -279,8 +288,9 @@ __global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a, int spw)
                         }
                         // row k+1 enters in the freed slot: [Y; 0]
                         const int i = k + 1;
-                        yr[Q] = (i < M && i < n) ? (double)Y[2 * (c * M + i)] : 0.0;
-                        yi[Q] = (i < M && i < n) ? (double)Y[2 * (c * M + i) + 1] : 0.0;
+                        const bool in = i < M && i < n;
+                        yr[Q] = in ? (double)yl[2 * (in ? i : 0)] : 0.0;
+                        yi[Q] = in ? (double)yl[2 * (in ? i : 0) + 1] : 0.0;
                     }
                 });
             }

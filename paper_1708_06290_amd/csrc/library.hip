@@ -440,7 +440,7 @@ hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const do
 hipError_t g_eval(shs_handle *h, int64_t s, const double *X, int64_t ldx, double *G, int64_t ldg, hipStream_t st)
 {
     if (s <= 0 || h->p <= 0) return hipSuccess;
-    hipLaunchKernelGGL(g_eval_kernel, dim3((unsigned)(s * h->m)), dim3(256), 0, st, (int)h->n, (int)h->p, (int)h->m,
+    hipLaunchKernelGGL(g_eval_kernel, dim3((unsigned)s), dim3(256), 0, st, (int)h->n, (int)h->p, (int)h->m,
                        (int)s, (const int32_t *)nullptr, (const double *)h->Ct, h->ldct, X, ldx, G, ldg);
     return hipGetLastError();
 }

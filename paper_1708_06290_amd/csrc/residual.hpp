@@ -288,59 +288,79 @@ __global__ __launch_bounds__(256) void eta_kernel(int n, int m, int count, const
     }
 }
 
-// G(:, col) = Ct X(:, col) for the columns of the listed shifts.
-// One workgroup per column; rows of Ct are taken 8 at a time.
+// G(:, sid m + c) = Ct X(:, sid m + c) for the listed shifts, one
+// workgroup per shift.  Thread t works on column c = t / TPC of the shift
+// (TPC = 256 / m rounded up to a power of two) and rows t % TPC, + TPC, ...:
+// the threads of one column read consecutive rows of X, and the shift's Ct
+// rows are read once per workgroup and shared by its m columns through the
+// caches (one workgroup per column re-read all of Ct for every column).
+// Outputs go 8 rows of G at a time; partial sums are added over the TPC
+// threads of a column in a fixed order (shuffles, then the waves in order),
+// so G does not depend on scheduling.
 __global__ __launch_bounds__(256) void g_eval_kernel(int n, int p, int m, int count, const int32_t *list,
                                                      const double *Ct, int64_t ldct,
                                                      const double *X, int64_t ldx,
                                                      double *G, int64_t ldg)
 {
     constexpr int PC = 8;
-    const int wi = blockIdx.x;            // work column = item * m + c
-    const int item = wi / m, c = wi % m;
+    const int item = blockIdx.x;
     if (item >= count) return;
     const int sid = list ? list[item] : item;
-    const int64_t col = (int64_t)sid * m + c;
+    int mp = 1;
+    while (mp < m) mp *= 2;
+    const int tpc = 256 / mp;                 // threads per column
+    const int tid = threadIdx.x, c = tid / tpc, r0 = tid % tpc;
+    const bool on = c < m;
+    const int64_t col = (int64_t)sid * m + (on ? c : 0);
     const double *x = X + col * ldx * 2;
-    __shared__ double red[PC * 2][256 / kWave];
-    const int tid = threadIdx.x;
-    for (int r0 = 0; r0 < p; r0 += PC) {
+    __shared__ double red[4][PC * 2][4];      // per wave: its columns' partial sums
+    for (int q0 = 0; q0 < p; q0 += PC) {
         double ar[PC], ai[PC];
 #pragma unroll
         for (int q = 0; q < PC; ++q) { ar[q] = 0.0; ai[q] = 0.0; }
-        for (int i = tid; i < n; i += 256) {
-            const double xr = x[2 * (int64_t)i], xi = x[2 * (int64_t)i + 1];
-            const double *cc = Ct + (int64_t)i * ldct + r0;
+        if (on) {
+            for (int i = r0; i < n; i += tpc) {
+                const double xr = x[2 * (int64_t)i], xi = x[2 * (int64_t)i + 1];
+                const double *cc = Ct + (int64_t)i * ldct + q0;
 #pragma unroll
-            for (int q = 0; q < PC; ++q) {
-                if (r0 + q < p) {
-                    const double cv = cc[q];
-                    ar[q] = fma(cv, xr, ar[q]);
-                    ai[q] = fma(cv, xi, ai[q]);
+                for (int q = 0; q < PC; ++q) {
+                    if (q0 + q < p) {
+                        const double cv = cc[q];
+                        ar[q] = fma(cv, xr, ar[q]);
+                        ai[q] = fma(cv, xi, ai[q]);
+                    }
                 }
             }
         }
-        // wave reduction then across the 4 waves
+        // sum over the lanes of one column inside the wave (tpc >= 16)
+        const int span = tpc < kWave ? tpc : kWave;
 #pragma unroll
         for (int q = 0; q < PC; ++q) {
-            for (int off = 32; off > 0; off >>= 1) {
+            for (int off = 1; off < span; off <<= 1) {
                 ar[q] += __shfl_xor(ar[q], off);
                 ai[q] += __shfl_xor(ai[q], off);
             }
         }
-        const int wv = tid / kWave;
-        if ((tid & 63) == 0) {
+        const int wv = tid / kWave, lane = tid % kWave;
+        // lane 0 of each column's span in this wave holds its partial sums
+        if (lane % span == 0) {
+            const int slot = lane / span;     // column slot inside the wave (< 64 / span <= 4)
 #pragma unroll
-            for (int q = 0; q < PC; ++q) { red[2 * q][wv] = ar[q]; red[2 * q + 1][wv] = ai[q]; }
+            for (int q = 0; q < PC; ++q) { red[wv][2 * q][slot] = ar[q]; red[wv][2 * q + 1][slot] = ai[q]; }
         }
         __syncthreads();
-        if (tid < 2 * PC) {
-            const int q = tid / 2;
-            if (r0 + q < p) {
+        // one thread per (column, output): add the waves that hold the column, in order
+        if (tid < m * 2 * PC) {
+            const int cc = tid / (2 * PC), e = tid % (2 * PC), q = e / 2;
+            if (q0 + q < p) {
+                const int t0 = cc * tpc;                  // first thread of column cc
+                const int w0 = t0 / kWave, nw = (tpc + kWave - 1) / kWave;
                 double sacc = 0.0;
-#pragma unroll
-                for (int w = 0; w < 256 / kWave; ++w) sacc += red[tid][w];
-                G[2 * (col * ldg + r0 + q) + (tid & 1)] = sacc;
+                for (int w = w0; w < w0 + nw; ++w) {
+                    const int slot = (t0 % kWave) / span;
+                    sacc += red[w][e][slot];
+                }
+                G[2 * (((int64_t)sid * m + cc) * ldg + q0 + q) + (e & 1)] = sacc;
             }
         }
         __syncthreads();

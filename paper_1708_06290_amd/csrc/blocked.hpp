@@ -287,29 +287,53 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
             // the older composite rows: B <- B M2 (real form)
             const int r1 = (a.D - a.gk + 1) * TT, nrows = (a.gk - 1) * TT;
             double *bb = a.Bm + (int64_t)r1 * a.ldb + item * W;
+            // each lane one row at a time: the whole row first (its loads in
+            // flight together; up to m = 8 the next row's are issued before
+            // this one is multiplied, beyond that the registers are short),
+            // then the product with M2 from LDS; the opaque offset keeps the
+            // compiler from hoisting all (2m)^2 LDS reads out of the row loop
+            // into registers
+            constexpr bool PF = M <= 8;
+            T o[2 * M];
+            if (PF && lane < nrows) {
+#pragma unroll
+                for (int q = 0; q < 2 * M; ++q) o[q] = bb[(int64_t)lane * a.ldb + q];
+            }
 #pragma unroll 1
             for (int p = lane; p < nrows; p += kWave) {
                 double *row = bb + (int64_t)p * a.ldb;
-                T nw[2 * M];
+                T on[2 * M], nw[2 * M];
+                const int pn = p + kWave < nrows ? p + kWave : p;
 #pragma unroll
-                for (int q = 0; q < 2 * M; ++q) nw[q] = T(0);
-#pragma unroll 1
                 for (int q = 0; q < 2 * M; ++q) {
-                    const T o = row[q];
-#pragma unroll
-                    for (int qq = 0; qq < 2 * M; ++qq) nw[qq] = fma(o, lds_m2[q * W + qq], nw[qq]);
+                    if constexpr (PF) on[q] = bb[(int64_t)pn * a.ldb + q];
+                    else o[q] = row[q];
+                    nw[q] = T(0);
                 }
+                int z = 0;
+                asm volatile("" : "+v"(z));
 #pragma unroll
-                for (int q = 0; q < 2 * M; ++q) row[q] = nw[q];
+                for (int q = 0; q < 2 * M; ++q)
+#pragma unroll
+                    for (int qq = 0; qq < 2 * M; ++qq) nw[qq] = fma(o[q], lds_m2[z + q * W + qq], nw[qq]);
+#pragma unroll
+                for (int q = 0; q < 2 * M; ++q) {
+                    row[q] = nw[q];
+                    if constexpr (PF) o[q] = on[q];
+                }
             }
             // M2q <- M2p M2
             const double *pa = a.M2p + (int64_t)item * W * W;
             double *pm = a.M2q + (int64_t)item * W * W;
             for (int e = lane; e < 4 * M * M; e += kWave) {
                 const int k = e / (2 * M), qq = e % (2 * M);
+                // row k of M2p first (its loads in flight together)
+                T r[2 * M];
+#pragma unroll
+                for (int q = 0; q < 2 * M; ++q) r[q] = pa[k * W + q];
                 T acc = T(0);
-#pragma unroll 1
-                for (int q = 0; q < 2 * M; ++q) acc = fma(pa[k * W + q], lds_m2[q * W + qq], acc);
+#pragma unroll
+                for (int q = 0; q < 2 * M; ++q) acc = fma(r[q], lds_m2[q * W + qq], acc);
                 pm[k * W + qq] = acc;
             }
         }

@@ -121,10 +121,20 @@ __device__ __forceinline__ const T *refl_slot(const T *rf, int k, int tt, int64_
 // (apply_step) takes zeros instead; the loads are so issued on every step,
 // and with no branch around them the waits for them count exactly the
 // memory operations issued since.
-template <typename T, int R>
+template <typename T, int M, int R>
 __device__ __forceinline__ void load_fresh(const T *H, int64_t ldh, int n, int lo, int lane, int col,
                                            T (&fr)[R])
 {
+    if constexpr (M == 1) {
+        // one-column windows in eight row slots: here the unconditional
+        // loads let the compiler keep too many of them live, so a negative
+        // col skips them (the waits are then counted less exactly)
+        if (col < 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) fr[r] = T(0);
+            return;
+        }
+    }
     const T *cp = H + (int64_t)(col < 0 ? 0 : col) * ldh;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -163,6 +173,12 @@ __device__ __forceinline__ void make_refl(const T (&pr)[M + 1], const T (&pi)[M 
     const T d = ph ? aa * um : um;
     const T q = d > T(0) ? T(1) / d : T(0);
     const T cr = (ph ? ar : T(1)) * q, ci = (ph ? ai : T(0)) * q;
+    tau = z ? T(0) : um / nu;
+    // beta = -ph nu (as conj(beta') e_m^T = w P), ph = (cr + i ci) um;
+    // w_m itself when P = I
+    const T s = nu * um;
+    br = z ? pr[M] : -cr * s;
+    bi = z ? pi[M] : ci * s;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         // conj(w_j) * conj(u_m) / |u_m|^2
@@ -170,12 +186,6 @@ __device__ __forceinline__ void make_refl(const T (&pr)[M + 1], const T (&pi)[M 
         vr[j] = fma(xr, cr, xi * ci);
         vi[j] = fma(xi, cr, -(xr * ci));
     }
-    tau = z ? T(0) : um / nu;
-    // beta = -ph nu (as conj(beta') e_m^T = w P), ph = (cr + i ci) um;
-    // w_m itself when P = I
-    const T s = nu * um;
-    br = z ? pr[M] : -cr * s;
-    bi = z ? pi[M] : ci * s;
 }
 
 // Apply P_k to row slots [0, RA) at phase Q = k mod (m+1), then slide: the
@@ -311,7 +321,7 @@ __device__ __forceinline__ void tri_step(int k, int k_lo, int n, int lo, int lan
 #pragma unroll
     for (int r = 0; r < R; ++r) ch[r] = nh[r];
     const int kn = k - 1 >= k_lo ? k - 1 : k_lo;
-    load_fresh<T, R>(H, ldh, n, lo, lane, kn - 1 - M, nh);
+    load_fresh<T, M, R>(H, ldh, n, lo, lane, kn - 1 - M, nh);
     T pr[NP], pi[NP], per[EM], pei[EM];
     if constexpr (RP < 0)
         pivot_row<T, M, R, EM, Q, DENSE>(wr, wi, er, ei, k - lo, pr, pi, per, pei);
@@ -400,7 +410,7 @@ __device__ __forceinline__ void tri_phase(int n, int lo, int hi, int lane, const
     if (hi - 1 >= k_end) {
         const int k_hi = hi - 1, k_lo = k_end;
         T nh[R];
-        load_fresh<T, R>(H, ldh, n, lo, lane, k_hi - 1 - M, nh);
+        load_fresh<T, M, R>(H, ldh, n, lo, lane, k_hi - 1 - M, nh);
         if constexpr (!SLOTS) {
             const int kg0 = k_hi + (M - k_hi % NP);   // group top: k = M (mod m+1)
             for (int kg = kg0; kg >= k_lo; kg -= NP) {
@@ -586,7 +596,7 @@ __device__ __forceinline__ void sweep_body(const SweepItem<T> &it, T *lds_refl, 
             };
             fetch(kb);
             T nh[R];
-            load_fresh<T, R>(H, ldh, n, lo, lane, k_hi - 1 - M, nh);
+            load_fresh<T, M, R>(H, ldh, n, lo, lane, k_hi - 1 - M, nh);
             for (; kb + KC - 1 >= k_lo; kb -= KC) {
                 // one wave per workgroup: its LDS operations complete in
                 // order, so the chunk can overwrite the previous one in place
@@ -605,7 +615,7 @@ __device__ __forceinline__ void sweep_body(const SweepItem<T> &it, T *lds_refl, 
 #pragma unroll
                         for (int r = 0; r < R; ++r) ch[r] = nh[r];
                         const int kn = k - 1 >= k_lo ? k - 1 : k_lo;
-                        load_fresh<T, R>(H, ldh, n, lo, lane, kn - 1 - M, nh);
+                        load_fresh<T, M, R>(H, ldh, n, lo, lane, kn - 1 - M, nh);
                         const T *p = lds_refl + (KC - 1 - st) * S;
                         T vr[M], vi[M], yr[EM], yi[EM];
                         const T tau = p[0];

@@ -118,9 +118,11 @@ int shs_reduce(int64_t n, int64_t m, int64_t p,
 
 /*
  * Exact number of bytes of device workspace shs_solve needs for `s` shifts
- * with the given mode and outputs (per-shift reflector store, the FP32
- * buffers of the mixed path, residual and bookkeeping).  The serving layer
- * admits work by this figure.
+ * with the given mode and outputs (per-shift reflector store, the carried
+ * columns and block transforms of the blocked FP64 sweep, the FP32 buffers
+ * of the mixed path, the packed copy of the solutions the residual GEMM
+ * reads, the residual and bookkeeping).  The serving layer admits work by
+ * this figure.
  */
 int shs_solve_workspace(const shs_handle *h, int64_t s, int mode, int outputs,
                         size_t *bytes);

@@ -289,20 +289,20 @@ __global__ __launch_bounds__(256) void eta_kernel(int n, int m, int count, const
 }
 
 // G(:, sid m + c) = Ct X(:, sid m + c) for the listed shifts, one
-// workgroup per shift.  Thread t works on column c = t / TPC of the shift
-// (TPC = 256 / m rounded up to a power of two) and rows t % TPC, + TPC, ...:
-// the threads of one column read consecutive rows of X, and the shift's Ct
-// rows are read once per workgroup and shared by its m columns through the
-// caches (one workgroup per column re-read all of Ct for every column).
-// Outputs go 8 rows of G at a time; partial sums are added over the TPC
-// threads of a column in a fixed order (shuffles, then the waves in order),
-// so G does not depend on scheduling.
+// workgroup per shift.  Rows go in chunks of 256: the chunk's rows of Ct (8
+// outputs at a time) are staged in LDS once for the shift's m columns, and
+// thread t works on column c = t / TPC (TPC = 256 / m rounded up to a power
+// of two) and rows t % TPC, + TPC, ... of the chunk, whose loads of X (the
+// threads of one column read consecutive rows) are all issued before they
+// are used.  Partial sums are added over the TPC threads of a column in a
+// fixed order (shuffles, then the waves in order), so G does not depend on
+// scheduling.
 __global__ __launch_bounds__(256) void g_eval_kernel(int n, int p, int m, int count, const int32_t *list,
                                                      const double *Ct, int64_t ldct,
                                                      const double *X, int64_t ldx,
                                                      double *G, int64_t ldg)
 {
-    constexpr int PC = 8;
+    constexpr int PC = 8, CH = 256, XL = CH / 16;   // rows per chunk; X loads per thread (TPC >= 16)
     const int item = blockIdx.x;
     if (item >= count) return;
     const int sid = list ? list[item] : item;
@@ -313,21 +313,36 @@ __global__ __launch_bounds__(256) void g_eval_kernel(int n, int p, int m, int co
     const bool on = c < m;
     const int64_t col = (int64_t)sid * m + (on ? c : 0);
     const double *x = X + col * ldx * 2;
+    __shared__ double cts[CH][PC];
     __shared__ double red[4][PC * 2][4];      // per wave: its columns' partial sums
     for (int q0 = 0; q0 < p; q0 += PC) {
         double ar[PC], ai[PC];
 #pragma unroll
         for (int q = 0; q < PC; ++q) { ar[q] = 0.0; ai[q] = 0.0; }
-        if (on) {
-            for (int i = r0; i < n; i += tpc) {
-                const double xr = x[2 * (int64_t)i], xi = x[2 * (int64_t)i + 1];
-                const double *cc = Ct + (int64_t)i * ldct + q0;
+        for (int i0 = 0; i0 < n; i0 += CH) {
+            __syncthreads();                  // the previous chunk is read
+            for (int e = tid; e < CH * PC; e += 256) {
+                const int i = i0 + e / PC, q = e % PC;
+                cts[e / PC][q] = (i < n && q0 + q < p) ? Ct[(int64_t)i * ldct + q0 + q] : 0.0;
+            }
+            double xr[XL], xi[XL];
 #pragma unroll
-                for (int q = 0; q < PC; ++q) {
-                    if (q0 + q < p) {
-                        const double cv = cc[q];
-                        ar[q] = fma(cv, xr, ar[q]);
-                        ai[q] = fma(cv, xi, ai[q]);
+            for (int l = 0; l < XL; ++l) {
+                const int ii = r0 + l * tpc, i = i0 + ii;
+                const bool ok = on && ii < CH && i < n;
+                xr[l] = ok ? x[2 * (int64_t)i] : 0.0;
+                xi[l] = ok ? x[2 * (int64_t)i + 1] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int l = 0; l < XL; ++l) {
+                const int ii = r0 + l * tpc;
+                if (ii < CH) {
+#pragma unroll
+                    for (int q = 0; q < PC; ++q) {
+                        const double cv = cts[ii][q];
+                        ar[q] = fma(cv, xr[l], ar[q]);
+                        ai[q] = fma(cv, xi[l], ai[q]);
                     }
                 }
             }

@@ -422,7 +422,7 @@ hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const do
     if (s_list <= 0) return hipGetLastError();
     // what the direct-to-LDS loads assume: 16-byte aligned pairs of rows
     if (n < 2 || h->ldh & 1 || ((uintptr_t)h->H | (uintptr_t)Xt) & 15) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(residual_pack_kernel, dim3(cdiv(residual_pack_rows(n), 64), ra.ldxt / 128), dim3(256), 0, st,
+    hipLaunchKernelGGL(residual_pack_kernel, dim3(cdiv(residual_pack_rows(n), 64), ra.ldxt / 64), dim3(256), 0, st,
                        ra);
     ps0.end();
     {

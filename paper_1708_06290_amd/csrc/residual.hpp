@@ -38,32 +38,40 @@ typedef double shs_dbl4 __attribute__((ext_vector_type(4)));
 // Xt(k, :) = the listed solutions, row k, k-major: complex column w (item
 // w / m, right-hand side w % m) is real column 16 (w / 8) + w % 8 (real part)
 // and 8 more (imaginary part), so every 16 real columns hold 8 whole complex
-// columns.  Rows n .. and columns past the list are zero.  A 64 x 64
-// complex tile goes through LDS: read along k (the columns of X), written
-// along the rows of Xt.
+// columns.  Rows n .. and columns past the list are zero.  A tile of 64 rows
+// x 32 complex columns goes through LDS (34 KB, four workgroups per CU): its
+// loads (along k, the columns of X) are all issued before the LDS stores,
+// and it is written along the rows of Xt.
 __global__ __launch_bounds__(256) void residual_pack_kernel(ResidualArgs a)
 {
-    __shared__ double tr[64][65], ti[64][65];
+    constexpr int TK = 64, TW = 32, PER = TK * TW / 256;   // complex values per thread
+    __shared__ double tr[TK][TW + 1], ti[TK][TW + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int k0 = blockIdx.x * 64, w0 = blockIdx.y * 64;
+    const int k0 = blockIdx.x * TK, w0 = blockIdx.y * TW;
     const int ncols = a.count * a.m, m = a.m;
-    for (int q = wave; q < 64; q += 4) {
-        const int w = w0 + q, k = k0 + lane;
-        double xr = 0.0, xi = 0.0;
+    double xr[PER], xi[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int q = wave + 4 * e, w = w0 + q, k = k0 + lane;
+        xr[e] = 0.0;
+        xi[e] = 0.0;
         if (w < ncols && k < a.n) {
             const int item = w / m, c = w % m;
             const int sid = a.list ? a.list[item] : item;
             const double *x = a.X + (((int64_t)sid * m + c) * a.ldx + k) * 2;
-            xr = x[0];
-            xi = x[1];
+            xr[e] = x[0];
+            xi[e] = x[1];
         }
-        tr[lane][q] = xr;
-        ti[lane][q] = xi;
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        tr[lane][wave + 4 * e] = xr[e];
+        ti[lane][wave + 4 * e] = xi[e];
     }
     __syncthreads();
     const int rows = (int)residual_pack_rows(a.n);
-    for (int e = tid; e < 64 * 128; e += 256) {
-        const int kk = e / 128, j = e % 128, k = k0 + kk;
+    for (int e = tid; e < TK * 2 * TW; e += 256) {
+        const int kk = e / (2 * TW), j = e % (2 * TW), k = k0 + kk;
         if (k >= rows) break;
         const int q = (j / 16) * 8 + j % 8;   // complex column in the tile
         const double v = (j % 16) < 8 ? tr[kk][q] : ti[kk][q];

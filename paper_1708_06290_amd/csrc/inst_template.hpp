@@ -34,7 +34,7 @@ struct Inst {
         } else if (a.count > 0) {
             // the kernel reads the structured store's slots (and needs a tile
             // of at least one phase group)
-            if (a.slot != slot_elems(MM, false) || a.tile_rows < MM + 1) return false;
+            if (a.slot != slot_elems(MM, false) || a.tile_rows < MM + 1 || a.accumulate) return false;
             const int spw = qstar_spw(a.count, MM);
             hipLaunchKernelGGL((qstar_wave_kernel<REAL_T, MM>), dim3((a.count + spw - 1) / spw), dim3(kWave), 0, st,
                                a, spw);

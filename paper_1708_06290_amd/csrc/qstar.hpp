@@ -160,8 +160,69 @@ __global__ __launch_bounds__(64) void qstar_kernel(QstarArgs<T> a)
 // the next chunk in flight while the current one is used), so the serial
 // chain of n steps does not wait on memory.  spw is chosen by the caller to
 // give about one wave per SIMD.  The inner product v^* y is summed in two
-// interleaved partial sums to halve its dependence chain.
+// interleaved partial sums to halve its dependence chain.  It writes X
+// (no accumulation: the mixed path's corrections use qstar_kernel).
 constexpr int kQstarLds = 1536;   // LDS elements of one chunk (all shifts)
+
+// Step k (phase Q = k mod (m+1)) of one lane of qstar_wave_kernel: apply
+// P_k (its slot at pv) to the window, emit row k-m into X and let row k+1
+// of [Y; 0] in.  GUARD handles the steps near the ends: k >= n only flushes,
+// rows outside 0 .. n-1 are not stored, rows below m come from Y.
+template <typename T, int M, int Q, bool GUARD>
+__device__ __forceinline__ void qstar_wave_step(int k, int n, const T *pv, const T *yl, double *X, double (&yr)[M + 1],
+                                                double (&yi)[M + 1])
+{
+    constexpr int NP = M + 1;
+    if (!GUARD || k < n) {
+        const double tau = (double)pv[0];
+        double vr[M], vi[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            vr[j] = (double)pv[2 + 2 * j];
+            vi[j] = (double)pv[3 + 2 * j];
+        }
+        // d = v^* y over rows k-m .. k (v_m = 1)
+        constexpr int pm = (M + Q) % NP;
+        double dr0 = yr[pm], di0 = yi[pm], dr1 = 0.0, di1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const int p = (j + Q) % NP;
+            if (j & 1) {
+                dr1 = fma(vr[j], yr[p], fma(vi[j], yi[p], dr1));
+                di1 = fma(vr[j], yi[p], fma(-vi[j], yr[p], di1));
+            } else {
+                dr0 = fma(vr[j], yr[p], fma(vi[j], yi[p], dr0));
+                di0 = fma(vr[j], yi[p], fma(-vi[j], yr[p], di0));
+            }
+        }
+        const double tr = tau * (dr0 + dr1), ti = tau * (di0 + di1);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const int p = (j + Q) % NP;
+            yr[p] = fma(-tr, vr[j], fma(ti, vi[j], yr[p]));
+            yi[p] = fma(-tr, vi[j], fma(-ti, vr[j], yi[p]));
+        }
+        yr[pm] -= tr;
+        yi[pm] -= ti;
+    }
+    // row k-m (logical 0, slot Q) is final
+    const int row = k - M;
+    if (!GUARD || (row >= 0 && row < n)) {
+        double *px = X + 2 * (int64_t)row;
+        px[0] = yr[Q];
+        px[1] = yi[Q];
+    }
+    // row k+1 enters in the freed slot: [Y; 0]
+    if constexpr (GUARD) {
+        const int i = k + 1;
+        const bool in = i < M && i < n;
+        yr[Q] = in ? (double)yl[2 * (in ? i : 0)] : 0.0;
+        yi[Q] = in ? (double)yl[2 * (in ? i : 0) + 1] : 0.0;
+    } else {
+        yr[Q] = 0.0;
+        yi[Q] = 0.0;
+    }
+}
 
 template <typename T, int M>
 __global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a, int spw)
@@ -190,7 +251,6 @@ __global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a, int spw)
     const int lsid = lact ? (a.list ? a.list[litem] : litem) : 0;
     const T *rf = a.refl + (int64_t)lsid * a.refl_stride;
     double *X = a.X + ((int64_t)sid * M + c) * a.ldx * 2;
-    const double sc = (a.accumulate && a.scale) ? a.scale[sid] : 1.0;
     const int ce_elems = CS * S;   // elements of one shift's chunk
     const int tt = a.tile_rows;
     T pre[PL];
@@ -237,62 +297,21 @@ __global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a, int spw)
             const T *base = lds_ch + q * RS;
             const int ce = min(k_last + 1, cb + CS);
             for (int kg = cb; kg < ce; kg += NP) {
-                static_for<NP>([&](auto qc) {
-                    constexpr int Q = decltype(qc)::value;   // k mod (m+1)
-                    const int k = kg + Q;
-                    if (k < ce) {
-                        if (k < n) {
-                            const T *pv = base + (k - cb) * S;
-                            const double tau = (double)pv[0];
-                            double vr[M], vi[M];
-#pragma unroll
-                            for (int j = 0; j < M; ++j) {
-                                vr[j] = (double)pv[2 + 2 * j];
-                                vi[j] = (double)pv[3 + 2 * j];
-                            }
-                            // d = v^* y over rows k-m .. k (v_m = 1)
-                            constexpr int pm = (M + Q) % NP;
-                            double dr0 = yr[pm], di0 = yi[pm], dr1 = 0.0, di1 = 0.0;
-#pragma unroll
-                            for (int j = 0; j < M; ++j) {
-                                const int p = (j + Q) % NP;
-                                if (j & 1) {
-                                    dr1 = fma(vr[j], yr[p], fma(vi[j], yi[p], dr1));
-                                    di1 = fma(vr[j], yi[p], fma(-vi[j], yr[p], di1));
-                                } else {
-                                    dr0 = fma(vr[j], yr[p], fma(vi[j], yi[p], dr0));
-                                    di0 = fma(vr[j], yi[p], fma(-vi[j], yr[p], di0));
-                                }
-                            }
-                            const double tr = tau * (dr0 + dr1), ti = tau * (di0 + di1);
-#pragma unroll
-                            for (int j = 0; j < M; ++j) {
-                                const int p = (j + Q) % NP;
-                                yr[p] = fma(-tr, vr[j], fma(ti, vi[j], yr[p]));
-                                yi[p] = fma(-tr, vi[j], fma(-ti, vr[j], yi[p]));
-                            }
-                            yr[pm] -= tr;
-                            yi[pm] -= ti;
-                        }
-                        // row k-m (logical 0, slot Q) is final
-                        const int row = k - M;
-                        if (row >= 0 && row < n) {
-                            double *px = X + 2 * (int64_t)row;
-                            if (a.accumulate) {
-                                px[0] += sc * yr[Q];
-                                px[1] += sc * yi[Q];
-                            } else {
-                                px[0] = yr[Q];
-                                px[1] = yi[Q];
-                            }
-                        }
-                        // row k+1 enters in the freed slot: [Y; 0]
-                        const int i = k + 1;
-                        const bool in = i < M && i < n;
-                        yr[Q] = in ? (double)yl[2 * (in ? i : 0)] : 0.0;
-                        yi[Q] = in ? (double)yl[2 * (in ? i : 0) + 1] : 0.0;
-                    }
-                });
+                if (kg >= M && kg + NP <= n && kg + NP <= ce) {
+                    // a whole phase group inside the matrix: no guards, so the
+                    // group is one straight block (the next step's LDS reads
+                    // can go ahead of this step's arithmetic)
+                    static_for<NP>([&](auto qc) {
+                        constexpr int Q = decltype(qc)::value;   // k mod (m+1)
+                        qstar_wave_step<T, M, Q, false>(kg + Q, n, base + (kg + Q - cb) * S, yl, X, yr, yi);
+                    });
+                } else {
+                    static_for<NP>([&](auto qc) {
+                        constexpr int Q = decltype(qc)::value;
+                        if (kg + Q < ce)
+                            qstar_wave_step<T, M, Q, true>(kg + Q, n, base + (kg + Q - cb) * S, yl, X, yr, yi);
+                    });
+                }
             }
         }
     }

@@ -49,6 +49,40 @@ template <typename T> __device__ inline T dsqrt(T x);
 template <> __device__ inline double dsqrt<double>(double x) { return sqrt(x); }
 template <> __device__ inline float dsqrt<float>(float x) { return sqrtf(x); }
 
+// 1/x and 1/sqrt(x) from the hardware estimates refined by Newton steps
+// (two in FP64, one in FP32): within an ulp or two, not correctly rounded,
+// and cheaper than the division and square root sequences.  For normal
+// positive x (the callers guard zero).
+template <typename T> __device__ inline T rcp_nr(T x);
+template <> __device__ inline double rcp_nr<double>(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+template <> __device__ inline float rcp_nr<float>(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+template <typename T> __device__ inline T rsq_nr(T x);
+template <> __device__ inline double rsq_nr<double>(double x)
+{
+    // y <- y + y (1 - x y^2) / 2
+    const double h = 0.5 * x;
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    return fma(y, fma(-h * y, y, 0.5), y);
+}
+template <> __device__ inline float rsq_nr<float>(float x)
+{
+    const float h = 0.5f * x;
+    const float y = __builtin_amdgcn_rsqf(x);
+    return fmaf(y, fmaf(-h * y, y, 0.5f), y);
+}
+
 // Non-negative doubles order like their bit patterns, which lets an
 // unsigned 64-bit atomic max act as a floating-point max.
 __device__ inline void atomic_max_nonneg(unsigned long long *addr, double v)

@@ -50,6 +50,8 @@
 
 #include <utility>
 
+#include <limits>
+
 #include "common.hpp"
 
 namespace shs {
@@ -151,8 +153,8 @@ __device__ __forceinline__ void load_fresh(const T *H, int64_t ldh, int n, int l
 //
 // With a = |alpha|, phase ph = alpha / a (1 when a = 0), nu = ||x|| and
 // u_m = ph (a + nu): ||u||^2 = 2 nu (a + nu), so tau = (a + nu) / nu, and
-// 1 / u_m = conj(ph) / (a + nu) = conj(alpha) / (a (a + nu)).  Two
-// divisions per reflector.
+// 1 / u_m = conj(ph) / (a + nu) = conj(alpha) / (a (a + nu)): two
+// reciprocal square roots and two reciprocals per reflector.
 template <typename T, int M>
 __device__ __forceinline__ void make_refl(const T (&pr)[M + 1], const T (&pi)[M + 1], T (&vr)[M], T (&vi)[M],
                                           T &tau, T &br, T &bi)
@@ -163,17 +165,22 @@ __device__ __forceinline__ void make_refl(const T (&pr)[M + 1], const T (&pi)[M 
     const T ar = pr[M], ai = -pi[M];
     // no branch for the already-reduced row (sig2 = 0): there x_j = 0, so v
     // comes out zero as long as the scale below is finite, and tau and beta
-    // are selected
+    // are selected.  Square roots and reciprocals come from the hardware
+    // estimates with Newton steps (rsq_nr, rcp_nr); an alpha below the
+    // smallest normal counts as zero (phase 1), which moves u_m by at most
+    // that much.
     const bool z = sig2 == T(0);
-    const T aa = dsqrt<T>(fma(ar, ar, ai * ai));
-    const T nu = dsqrt<T>(fma(aa, aa, sig2));
-    const T um = aa + nu;                // |u_m|
-    const bool ph = aa > T(0);
+    const T a2 = fma(ar, ar, ai * ai), n2 = a2 + sig2;
+    const bool ph = a2 >= std::numeric_limits<T>::min();
+    const T ia = ph ? rsq_nr<T>(ph ? a2 : T(1)) : T(0);    // 1 / |alpha|
+    const T aa = a2 * ia;                                  // |alpha|
+    const bool nz = n2 >= std::numeric_limits<T>::min();
+    const T nu = nz ? n2 * rsq_nr<T>(nz ? n2 : T(1)) : T(0);   // ||x||
+    const T um = aa + nu;                                  // |u_m|
+    const T ru = um > T(0) ? rcp_nr<T>(um > T(0) ? um : T(1)) : T(0);
     // cr - i ci = conj(u_m) / |u_m|^2 = conj(ph) / um (zero for a zero row)
-    const T d = ph ? aa * um : um;
-    const T q = d > T(0) ? T(1) / d : T(0);
-    const T cr = (ph ? ar : T(1)) * q, ci = (ph ? ai : T(0)) * q;
-    tau = z ? T(0) : um / nu;
+    const T cr = ph ? ar * ia * ru : ru, ci = ph ? ai * ia * ru : T(0);
+    tau = z ? T(0) : um * rcp_nr<T>(nz ? nu : T(1));
     // beta = -ph nu (as conj(beta') e_m^T = w P), ph = (cr + i ci) um;
     // w_m itself when P = I
     const T s = nu * um;

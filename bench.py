@@ -297,10 +297,26 @@ def serving_leg(args):
     red_ms = [round(sy.info()["reduce_ms"], 1) for sy in systems]
     print(f"# serving: {len(systems)} systems reduced in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
 
-    def run(reqs, rate_hz, label):
+    def run(reqs, rate_hz, label, keep=6):
+        """Submit the stream; completed requests are checked (eta) and their
+        outputs released as the stream goes, except the first `keep`, so
+        long streams fit in device memory."""
         srv = ss.Server(streams=4, budget_bytes=64 << 30, max_batch=64)
         ids = [srv.register(sy) for sy in systems]
-        handles = []
+        kept, pending = [], []
+        bad = 0
+
+        def settle(h, block):
+            nonlocal bad
+            if block:
+                srv.wait(h, timeout_ms=600000)
+            elif srv.poll(h) < 2:
+                return False
+            e = h.eta.cpu().numpy() if h.eta is not None else None
+            if e is not None and not (e <= 1e-13).all():
+                bad += 1
+            return True
+
         t_start = time.perf_counter()
         for (t_arr, sys_id, shifts, mode) in reqs:
             if rate_hz is not None:
@@ -308,16 +324,19 @@ def serving_leg(args):
                 if delay > 0:
                     time.sleep(delay)
             md = ss.SHS_MODE_FP64 if mode == "fp64" else ss.SHS_MODE_FP32_REFINE
-            handles.append((srv.submit(ids[sys_id], shifts, mode=md), sys_id, shifts, mode))
-        for (h, _, _, _) in handles:
+            h = srv.submit(ids[sys_id], shifts, mode=md)
+            if len(kept) < keep:
+                kept.append((h, sys_id, shifts, mode))
+            pending.append(h)
+            while pending and settle(pending[0], False):
+                pending.pop(0)
+        for h in pending:
+            settle(h, True)
+        for (h, _, _, _) in kept:
             srv.wait(h, timeout_ms=600000)
         el = time.perf_counter() - t_start
         st = srv.stats()
-        bad = 0
-        for (h, _, _, _) in handles:
-            e = h.eta.cpu().numpy() if h.eta is not None else None
-            if e is not None and not (e <= 1e-13).all():
-                bad += 1
+        handles = kept
         out = {"requests": len(reqs), "rate_hz": rate_hz, "wall_s": round(el, 3),
                "solves_per_s": round(st["solves"] / el, 2), "p50_ms": round(st["p50_ms"], 2),
                "p99_ms": round(st["p99_ms"], 2), "max_ms": round(st["max_ms"], 2),

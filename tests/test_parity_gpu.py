@@ -69,6 +69,8 @@ CASES = [
     (1200, 4, 2, 3, 20),
     (1100, 6, 3, 2, 21),
     (400, 16, 4, 2, 22),
+    # more outputs than one pass of the G kernel takes (8 rows of G at a time)
+    (260, 5, 11, 3, 23),
 ]
 
 

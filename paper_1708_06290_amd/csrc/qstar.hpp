@@ -275,7 +275,8 @@ __global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a, int spw)
         for (int e = ll; e < 2 * M * M; e += gl) lds_y[lq * 2 * M * M + e] = ys[e];
     }
     __syncthreads();
-    const T *yl = lds_y + q * 2 * M * M + 2 * c * M;   // Y(:, c) of this lane's shift
+    // Y(:, c) of this lane's shift (idle lanes, q >= spw, point at shift 0's)
+    const T *yl = lds_y + (q < spw ? q : 0) * 2 * M * M + 2 * c * M;
     double yr[NP], yi[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) { yr[j] = 0.0; yi[j] = 0.0; }

@@ -152,7 +152,8 @@ int shs_solve_workspace(const shs_handle *h, int64_t s, int mode, int outputs,
  *
  * Asynchronous on `stream` except in mixed mode, which synchronises the
  * stream between refinement iterations to decide which shifts continue.
- * One solve per handle at a time per stream.
+ * One solve per handle at a time per stream.  s = 0 returns 0 at once,
+ * without looking at the output pointers.
  */
 int shs_solve(shs_handle *h, int64_t s, const double *shifts,
               int mode, int outputs, double tol, int max_iter,

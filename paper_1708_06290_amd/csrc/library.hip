@@ -783,11 +783,11 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outp
     if (!(outputs & (SHS_OUT_X | SHS_OUT_G))) return -5;
     if (mode == SHS_MODE_FP32_REFINE && !(tol > 0.0)) return -6;
     if (max_iter < 0) return -7;
+    if (s == 0) return 0;   // nothing to do; the output pointers are not referenced
     if ((outputs & SHS_OUT_X) && (!X || ldx < h->n)) return -10;
     if ((outputs & SHS_OUT_G) && h->p > 0 && (!G || ldg < h->p)) return -12;
     if (((outputs & SHS_OUT_ETA) || mode == SHS_MODE_FP32_REFINE) && !eta) return -14;
     if (!status) return -15;
-    if (s == 0) return 0;
     hipStream_t st = (hipStream_t)stream;
     const int64_t n = h->n, m = h->m;
     Layout L;

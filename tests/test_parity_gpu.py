@@ -291,3 +291,29 @@ def test_many_shifts_per_wave(n, m, s, mode):
     H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
     Xo, _, _, _ = oracle.solve(H, R, Ct, shifts[idx])
     _check_against(X[:, cols], Xo, m)
+
+
+def test_empty_shift_list_and_argument_errors():
+    """No shifts: nothing runs and the outputs are empty, in both modes; a
+    bad argument is refused with the LAPACK-style code and leaves the
+    handle usable."""
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    from paper_1708_06290_amd import _lib
+    n, m, p = 130, 3, 2
+    A, B, C = workloads.system(n, m, p, 49)
+    sysm = ss.System(A, B, C)
+    for mode in (ss.SHS_MODE_FP64, ss.SHS_MODE_FP32_REFINE):
+        res = sysm.solve(np.zeros(0, dtype=complex), mode=mode)
+        torch.cuda.synchronize()
+        assert res.X.shape == (n, 0) and res.G.shape == (p, 0) and res.status.numel() == 0
+    with pytest.raises(_lib.ShsError) as err:
+        _lib.shs_solve_workspace(sysm.handle, -1, ss.SHS_MODE_FP64, ss.SHS_OUT_X)
+    assert err.value.code == -2   # argument 2 (s) is invalid
+    shifts = workloads.imag_axis_shifts(1e-1, 1e1, 3)
+    res = sysm.solve(shifts)
+    torch.cuda.synchronize()
+    assert (res.status.cpu().numpy() == 0).all()
+    H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
+    Xo, _, _, _ = oracle.solve(H, R, Ct, shifts)
+    _check_against(res.X.cpu().numpy(), Xo, m)

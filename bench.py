@@ -80,14 +80,14 @@ def residual_flops(n: int, m: int) -> float:
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--mode", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle shifts (0 = automatic)")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink n and s (smoke runs only)")
-    ap.add_argument("--serve-requests", type=int, default=150,
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests per load level in the serving leg (0 = skip the leg)")
     ap.add_argument("--serve-scale", type=float, default=1.0, help="scale n of the serving systems")
     ap.add_argument("--serve-only", action="store_true")
@@ -146,13 +146,17 @@ def main():
         del src, dst
     results = {}
     modes = ["fp64", "mixed"] if args.mode == "both" else [args.mode]
+    if "fp64" in modes:
+        modes = ["fp64_uncertified"] + modes
     for mode_name in modes:
-        mode = ss.SHS_MODE_FP64 if mode_name == "fp64" else ss.SHS_MODE_FP32_REFINE
-        wbytes = sysm.workspace_bytes(s, mode, outputs)
+        mode = ss.SHS_MODE_FP32_REFINE if mode_name == "mixed" else ss.SHS_MODE_FP64
+        # the uncertified FP64 form skips the residual GEMM and eta
+        outs = (ss.SHS_OUT_X | ss.SHS_OUT_G) if mode_name == "fp64_uncertified" else outputs
+        wbytes = sysm.workspace_bytes(s, mode, outs)
         work = torch.empty(wbytes, dtype=torch.uint8, device=dev)
 
         def step():
-            ss.shs_solve(sysm.handle, dshifts, Xs, Gs, eta, status, mode=mode, outputs=outputs,
+            ss.shs_solve(sysm.handle, dshifts, Xs, Gs, eta, status, mode=mode, outputs=outs,
                          tol=1e-13, max_iter=5, work=work, stream=stream)
 
         sysm.set_timing(False)
@@ -161,22 +165,32 @@ def main():
         torch.cuda.synchronize()
         sysm.set_timing(True)
         phase = {}
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
         t1 = time.perf_counter()
-        for _ in range(args.steps):
+        for (ea, eb) in evs:
+            ea.record(stream)
             step()
+            eb.record(stream)
             tm = sysm.last_timings()      # waits for this step's last event only
             for k, v in tm.items():
                 phase[k] = phase.get(k, 0) + v
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
         sysm.set_timing(False)
+        step_ms = np.array([ea.elapsed_time(eb) for (ea, eb) in evs])
         e = eta.cpu().numpy()
         st = status.cpu().numpy()
+        certified = mode_name != "fp64_uncertified"
         results[mode_name] = {
             "solves_per_s": s * args.steps / el,
             "ms_per_step": 1e3 * el / args.steps,
-            "eta_max": float(np.nanmax(e)) if e.size else 0.0,
-            "certified": bool((e <= 1e-13).all()),
+            # per-step device time (HIP events around each solve)
+            "step_ms_median": round(float(np.median(step_ms)), 3),
+            "step_ms_p99": round(float(np.percentile(step_ms, 99)), 3),
+            "solves_per_s_median": round(s / (float(np.median(step_ms)) * 1e-3), 2),
+            "eta_max": (float(np.nanmax(e)) if e.size else 0.0) if certified else None,
+            "certified": bool((e <= 1e-13).all()) if certified else False,
             "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
             "phase_ms_per_step": {k: v / args.steps for k, v in phase.items() if k.endswith("_ms")},
             "launches_per_step": {k: v / args.steps for k, v in phase.items() if k.endswith("_calls")},
@@ -213,9 +227,14 @@ def main():
                 continue
             achieved = fl / (ms * 1e-3) / 1e12
             tb = traffic.get(name)
+            # measured HBM bytes per launch over the average launch time,
+            # against the 8 TB/s HBM peak
+            gbs = None if tb is None else tb / (ms / nl * 1e-3) / 1e9
             kernels[name] = {"bound": bound, "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                              "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                              "traffic": None if tb is None else round(tb),
+                             "hbm_gbs": None if gbs is None else round(gbs, 1),
+                             "hbm_frac": None if gbs is None else round(gbs / HBM_PEAK_GBS, 4),
                              "ms_per_step": round(ms, 3), "launches_per_step": nl,
                              "avg_launch_ms": round(ms / nl, 4), "flops_per_launch": fl / nl}
         if kernels:
@@ -275,6 +294,7 @@ def main():
         "mixed_kernels": mixed_kernels,
         "cpu_baseline": cpu,
         "fp64": results.get("fp64"),
+        "fp64_uncertified": results.get("fp64_uncertified"),
         "mixed": results.get("mixed"),
         "serving": serving,
     }
@@ -318,13 +338,16 @@ def serving_leg(args):
             return True
 
         t_start = time.perf_counter()
+        c_start = ss.shs_server_clock()
         for (t_arr, sys_id, shifts, mode) in reqs:
             if rate_hz is not None:
                 delay = t_arr - (time.perf_counter() - t_start)
                 if delay > 0:
                     time.sleep(delay)
             md = ss.SHS_MODE_FP64 if mode == "fp64" else ss.SHS_MODE_FP32_REFINE
-            h = srv.submit(ids[sys_id], shifts, mode=md)
+            # latency runs from the scheduled arrival, so any lag of this
+            # submitting loop counts against the server
+            h = srv.submit(ids[sys_id], shifts, mode=md, arrival_s=c_start + t_arr if rate_hz is not None else 0.0)
             if len(kept) < keep:
                 kept.append((h, sys_id, shifts, mode))
             pending.append(h)
@@ -340,7 +363,9 @@ def serving_leg(args):
         out = {"requests": len(reqs), "rate_hz": rate_hz, "wall_s": round(el, 3),
                "solves_per_s": round(st["solves"] / el, 2), "p50_ms": round(st["p50_ms"], 2),
                "p99_ms": round(st["p99_ms"], 2), "max_ms": round(st["max_ms"], 2),
+               "latency_from": "arrival" if rate_hz is not None else "submit",
                "batches": st["batches"], "max_batch_systems": st["max_batch_systems"],
+               "max_batch_requests": st["max_batch_requests"],
                "failed": st["failed"], "uncertified": bad}
         print(f"# serving {label}: {out}", file=sys.stderr, flush=True)
         return out, handles, srv, ids
@@ -360,15 +385,14 @@ def serving_leg(args):
             keep = (handles[:6], srv, ids)
         else:
             srv.close()
-    # the same requests alone on the idle server: FP64 results must be
-    # bitwise equal to the mix
+    # the same requests alone on the idle server: results must be bitwise
+    # equal to the mix (both modes)
     handles, srv, ids = keep
     same = 0
     checked = 0
     for (h, sys_id, shifts, mode) in handles:
-        if mode != "fp64":
-            continue
-        alone = srv.wait(srv.submit(ids[sys_id], shifts, mode=ss.SHS_MODE_FP64), timeout_ms=600000)
+        md = ss.SHS_MODE_FP64 if mode == "fp64" else ss.SHS_MODE_FP32_REFINE
+        alone = srv.wait(srv.submit(ids[sys_id], shifts, mode=md), timeout_ms=600000)
         torch.cuda.synchronize()
         checked += 1
         same += int(torch.equal(alone.X, h.X.t()))
@@ -395,7 +419,16 @@ def cpu_baseline(sysm, shifts, sample, n, m):
     t0 = time.perf_counter()
     oracle.solve(H, R, Ct, shifts[idx], nthreads=threads)
     el = time.perf_counter() - t0
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(len(idx) / el, 4), "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": f"{len(idx)} of {len(shifts)} shifts (spread evenly), reduced system (H, R, Ct) "
                       f"from the GPU reduction, {el:.1f} s"}
 

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SHS_ABI_VERSION 1
+#define SHS_ABI_VERSION 2
 
 /* return codes (positive) */
 #define SHS_ERR_NOMEM        1  /* device allocation failed or budget exceeded */
@@ -57,13 +57,15 @@ extern "C" {
 #define SHS_ERR_BUSY         4  /* resource in use (serving: queue full) */
 #define SHS_ERR_NOTFOUND     5  /* unknown id (serving) */
 #define SHS_ERR_TIMEOUT      6  /* wait timed out (serving) */
+#define SHS_ERR_CANCELLED    7  /* the request was cancelled (serving) */
+#define SHS_ERR_STATE        8  /* the request is not in a state that allows the call (serving) */
 
 /* per-shift status codes written by shs_solve */
 #define SHS_STATUS_OK             0
 #define SHS_STATUS_SINGULAR       1  /* a diagonal entry of R_sigma is exactly 0 */
 #define SHS_STATUS_NONFINITE      2  /* a NaN or Inf appeared in the result */
-#define SHS_STATUS_FALLBACK       3  /* mixed precision did not converge; FP64 result */
-#define SHS_STATUS_NOT_CONVERGED  4  /* refinement stopped above tol, no fallback */
+#define SHS_STATUS_FALLBACK       3  /* mixed precision did not converge; FP64 result meets tol */
+#define SHS_STATUS_NOT_CONVERGED  4  /* mixed precision: even the FP64 result is above tol */
 
 /* solve modes */
 #define SHS_MODE_FP64         0  /* FP64 sweep */
@@ -117,6 +119,19 @@ int shs_reduce(int64_t n, int64_t m, int64_t p,
                const shs_config *cfg, void *stream, shs_handle **out);
 
 /*
+ * Host-only check of the blocked reduction's launch plan for an n x n system
+ * with m inputs and p outputs (the GEMM updates of Algorithms 2-3): the
+ * sequence of launches shs_reduce would make is generated without a GPU, and
+ * every GEMM's grid, split-K partials and operand extents are checked
+ * against the allocations shs_reduce makes.  Returns the number of
+ * violations (0: every launch stays inside its buffers), negative for bad
+ * arguments; *launches (nullable) receives the number of GEMM launches and
+ * msg (msg_len bytes, nullable) the first violation, if any.  Touches no
+ * device.
+ */
+int shs_reduce_check_plan(int64_t n, int64_t m, int64_t p, int64_t *launches, char *msg, int64_t msg_len);
+
+/*
  * Exact number of bytes of device workspace shs_solve needs for `s` shifts
  * with the given mode and outputs (per-shift reflector store, the carried
  * columns and block transforms of the blocked FP64 sweep, the FP32 buffers
@@ -150,10 +165,16 @@ int shs_solve_workspace(const shs_handle *h, int64_t s, int mode, int outputs,
  *   status     device, s int32 SHS_STATUS_* codes, always written.  A bad
  *              shift never fails the call; its outputs are NaN.
  *
- * Asynchronous on `stream` except in mixed mode, which synchronises the
- * stream between refinement iterations to decide which shifts continue.
- * One solve per handle at a time per stream.  s = 0 returns 0 at once,
- * without looking at the output pointers.
+ * Mixed mode: the FP32 sweep result is refined until eta <= tol, a shift
+ * at a time; a shift whose eta is NaN, does not at least halve per round, or
+ * is still above tol after max_iter corrections is recomputed by the FP64
+ * sweep (status FALLBACK, or NOT_CONVERGED if that result is above tol as
+ * well).  max_iter = 0 sends every shift to the FP64 sweep.
+ *
+ * Asynchronous on `stream` in both modes: the host never waits inside the
+ * call (mixed mode keeps its per-shift lists on the device).  One solve per
+ * handle at a time per stream.  s = 0 returns 0 at once, without looking at
+ * the output pointers.
  */
 int shs_solve(shs_handle *h, int64_t s, const double *shifts,
               int mode, int outputs, double tol, int max_iter,
@@ -239,9 +260,17 @@ int shs_last_timings(const shs_handle *h, shs_timings_t *out);
  * run are admitted as workers and memory free up, so their work overlaps on
  * the device.  Latency is stamped at submit and at completion.
  *
- * Thread-safe: any thread may submit, poll and wait.  The server never owns
- * the handles it serves; destroy the server before them.  Do not enable
- * phase timing (shs_set_timing) on a handle a server uses.
+ * A request on the solve route (mixed mode, or FP64 above blocked_flops)
+ * is batched with the other waiting requests of the same system, mode and
+ * outputs into one shs_solve over all their shifts.  Every kernel computes
+ * each shift independently of the other shifts in its launch, so a result
+ * is bitwise the same alone and in any batch.  Latency runs from the
+ * request's arrival (given by the caller, else the submit call) to the end
+ * of its batch.
+ *
+ * Thread-safe: any thread may submit, poll, wait and cancel.  The server
+ * never owns the handles it serves; destroy the server before them.  Do not
+ * enable phase timing (shs_set_timing) on a handle a server uses.
  */
 typedef struct shs_server shs_server;
 
@@ -259,15 +288,34 @@ typedef struct shs_server_config {
     int64_t reserved[3];
 } shs_server_config;
 
+/* request states (shs_server_poll) */
+#define SHS_REQ_QUEUED     0
+#define SHS_REQ_RUNNING    1
+#define SHS_REQ_DONE       2
+#define SHS_REQ_FAILED     3
+#define SHS_REQ_CANCELLED  4
+
 typedef struct shs_server_stats_t {
-    int64_t submitted, completed, failed, queued, running;
+    int64_t submitted, completed, failed, cancelled, queued, running;
     int64_t solves;              /* shifts completed */
-    int64_t batches;             /* FP64 work-item launches */
-    int64_t max_batch_systems;   /* most distinct systems in one launch */
-    double  p50_ms, p99_ms, max_ms, mean_ms;   /* submit -> completion */
-    double  busy_s;              /* wall time from first submit to last completion */
+    int64_t batches;             /* launches of batched requests (both routes) */
+    int64_t max_batch_systems;   /* most distinct systems in one batch */
+    int64_t max_batch_requests;  /* most requests in one batch */
+    double  p50_ms, p99_ms, max_ms, mean_ms;   /* arrival -> completion of completed requests */
+    double  busy_s;              /* wall time from the first arrival to the last completion */
     int64_t peak_bytes;          /* largest admitted workspace total */
 } shs_server_stats_t;
+
+/* Options of one request (shs_server_submit_ex). */
+typedef struct shs_request_opts {
+    int32_t abi_version;   /* must be SHS_ABI_VERSION */
+    int32_t order_after;   /* 1: the request's work starts after all work queued on after_stream
+                              before the submit call (e.g. the allocation of its outputs); 0: no ordering */
+    void   *after_stream;  /* hipStream_t (NULL = the null stream), used when order_after = 1 */
+    double  arrival_s;     /* arrival time on the shs_server_clock() clock; <= 0 or later than
+                              the submit call: the submit call's time */
+    int64_t reserved[4];   /* 0 */
+} shs_request_opts;
 
 int shs_server_create(const shs_server_config *cfg, shs_server **out);
 
@@ -286,14 +334,36 @@ int shs_server_submit(shs_server *srv, int32_t sys_id, int64_t s, const double *
                       int mode, int outputs, double *X, int64_t ldx, double *G, int64_t ldg,
                       double *eta, int32_t *status, int64_t *req_id);
 
-/* *state: 0 queued, 1 running, 2 done, 3 failed. */
+/* As shs_server_submit, with options (NULL: none): ordering after the
+ * caller's stream and the request's arrival time.  -13 for a bad opts. */
+int shs_server_submit_ex(shs_server *srv, int32_t sys_id, int64_t s, const double *shifts_host,
+                         int mode, int outputs, double *X, int64_t ldx, double *G, int64_t ldg,
+                         double *eta, int32_t *status, const shs_request_opts *opts,
+                         int64_t *req_id);
+
+/* The server's clock (steady, seconds) for arrival times. */
+double shs_server_clock(void);
+
+/* *state: one of SHS_REQ_*. */
 int shs_server_poll(shs_server *srv, int64_t req_id, int *state);
 
 /* Wait until the request completes (timeout_ms < 0: no limit).  Returns 0,
- * SHS_ERR_TIMEOUT, or the error the request failed with. */
+ * SHS_ERR_TIMEOUT, SHS_ERR_CANCELLED, or the error the request failed with. */
 int shs_server_wait(shs_server *srv, int64_t req_id, double timeout_ms);
 
-/* Submit -> completion latency of a completed request, milliseconds. */
+/* Cancel a request.  A queued request is removed from the queue (its outputs
+ * are not touched) and is cancelled at once; a running one completes (its
+ * outputs may be written) and is then marked cancelled; either way it does
+ * not count as completed.  SHS_ERR_STATE if it already finished. */
+int shs_server_cancel(shs_server *srv, int64_t req_id);
+
+/* Hold (paused = 1) or release (0) the workers: while held, they start no
+ * new batch (running batches finish); requests queue up and are batched
+ * together on release. */
+int shs_server_pause(shs_server *srv, int paused);
+
+/* Arrival -> completion latency of a completed request, milliseconds;
+ * SHS_ERR_STATE if it has not completed. */
 int shs_server_latency(shs_server *srv, int64_t req_id, double *ms);
 
 int shs_server_stats(shs_server *srv, shs_server_stats_t *out);

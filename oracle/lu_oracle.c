@@ -28,9 +28,13 @@
  *  - a zero pivot marks the shift SINGULAR (status 1) and leaves NaNs in its
  *    outputs; other shifts are unaffected.
  *
- * The normwise backward error of each computed X_j is also reported:
- *   eta_j = max_c ||r_c||_inf / (||A - sigma_j I||_inf ||x_c||_inf + ||b_c||_inf)
- *   with r = B - (A - sigma_j I) X_j evaluated in double precision.
+ * A second entry point, oracle_solve_rhs, solves op(A - sigma_j I) X_j = F_j
+ * with a right-hand side block F_j of its own for every shift and op either
+ * the identity or the transpose (not the conjugate transpose).  These are the
+ * two families of systems Section 3.3 needs for the interpolation method of
+ * Section 1: (A - sigma I) x = B b_hat with a per-shift direction b_hat, and
+ * the transposed systems (A - sigma I)^T x = C^T c_hat.  The same elimination
+ * runs on the explicitly formed matrix op(A) - sigma I.
  *
  * All matrices are column-major double precision; complex arrays are
  * interleaved (re, im) pairs, i.e. C99 `double complex`.
@@ -48,26 +52,25 @@ typedef double complex zc;
 
 static double zabs(zc z) { return hypot(creal(z), cimag(z)); }
 
-/* One shift: returns 0 on success, 1 if a pivot was exactly zero,
- * -1 if the work arrays could not be allocated. */
-static int solve_one(int64_t n, int64_t m, int64_t p,
-                     const double *A, int64_t lda,
-                     const double *B, int64_t ldb,
-                     const double *C, int64_t ldc,
-                     zc sigma, zc *X, int64_t ldx, zc *G, int64_t ldg,
-                     double *eta_out)
+/* One shift: op(A) - sigma I is eliminated with the n x m right-hand side F0
+ * (complex, ld ldf) or, if F0 is NULL, the real B (ld ldb).  Returns 0 on
+ * success, 1 if a pivot was exactly zero, -1 if the work arrays could not be
+ * allocated.  The solution goes to X (ld ldx). */
+static int solve_one(int64_t n, int64_t m, const double *A, int64_t lda, int trans,
+                     const double *B, int64_t ldb, const zc *F0, int64_t ldf,
+                     zc sigma, zc *X, int64_t ldx)
 {
     zc *M = (zc *)malloc(sizeof(zc) * (size_t)n * (size_t)n);
     zc *F = (zc *)malloc(sizeof(zc) * (size_t)n * (size_t)(m > 0 ? m : 1));
     if (!M || !F) { free(M); free(F); return -1; }
 
-    /* M = A - sigma I, F = B */
+    /* M = op(A) - sigma I, F = B or F0 */
     for (int64_t j = 0; j < n; ++j) {
-        for (int64_t i = 0; i < n; ++i) M[i + j * n] = A[i + j * lda];
+        for (int64_t i = 0; i < n; ++i) M[i + j * n] = trans ? A[j + i * lda] : A[i + j * lda];
         M[j + j * n] -= sigma;
     }
     for (int64_t c = 0; c < m; ++c)
-        for (int64_t i = 0; i < n; ++i) F[i + c * n] = B[i + c * ldb];
+        for (int64_t i = 0; i < n; ++i) F[i + c * n] = F0 ? F0[i + c * ldf] : B[i + c * ldb];
 
     int status = 0;
     for (int64_t k = 0; k < n; ++k) {
@@ -113,9 +116,6 @@ static int solve_one(int64_t n, int64_t m, int64_t p,
     if (status != 0) {
         for (int64_t c = 0; c < m; ++c)
             for (int64_t i = 0; i < n; ++i) X[i + c * ldx] = NAN + NAN * I;
-        for (int64_t c = 0; c < m; ++c)
-            for (int64_t i = 0; i < p; ++i) G[i + c * ldg] = NAN + NAN * I;
-        if (eta_out) *eta_out = NAN;
         free(M); free(F);
         return status;
     }
@@ -132,58 +132,15 @@ static int solve_one(int64_t n, int64_t m, int64_t p,
         for (int64_t i = 0; i < n; ++i) X[i + c * ldx] = f[i];
     }
 
-    /* G = C X */
-    for (int64_t c = 0; c < m; ++c)
-        for (int64_t i = 0; i < p; ++i) {
-            zc acc = 0.0;
-            for (int64_t k = 0; k < n; ++k) acc += C[i + k * ldc] * X[k + c * ldx];
-            G[i + c * ldg] = acc;
-        }
-
-    /* normwise backward error, residual r = B - (A - sigma I) X */
-    if (eta_out) {
-        double anorm = 0.0;               /* ||A - sigma I||_inf */
-        for (int64_t i = 0; i < n; ++i) {
-            double row = 0.0;
-            for (int64_t j = 0; j < n; ++j) {
-                zc a = A[i + j * lda];
-                if (i == j) a -= sigma;
-                row += zabs(a);
-            }
-            if (row > anorm) anorm = row;
-        }
-        double eta = 0.0;
-        for (int64_t c = 0; c < m; ++c) {
-            double rmax = 0.0, xmax = 0.0, bmax = 0.0;
-            for (int64_t i = 0; i < n; ++i) {
-                zc acc = B[i + c * ldb];
-                for (int64_t j = 0; j < n; ++j) {
-                    double a = A[i + j * lda];
-                    if (a != 0.0) acc -= a * X[j + c * ldx];
-                }
-                acc += sigma * X[i + c * ldx];
-                double ra = zabs(acc);
-                if (ra > rmax) rmax = ra;
-                double xa = zabs(X[i + c * ldx]);
-                if (xa > xmax) xmax = xa;
-                double ba = fabs(B[i + c * ldb]);
-                if (ba > bmax) bmax = ba;
-            }
-            double den = anorm * xmax + bmax;
-            double e = den > 0.0 ? rmax / den : (rmax > 0.0 ? INFINITY : 0.0);
-            if (e > eta) eta = e;
-        }
-        *eta_out = eta;
-    }
     free(M); free(F);
     return 0;
 }
 
 /*
- * Solve all s shifts.  X is n x (s*m) with X(:, j*m:(j+1)*m) = X_j, G is
- * p x (s*m) likewise; eta (length s, nullable) and status (length s) are per
- * shift.  nthreads <= 0 uses the OpenMP default.  Returns 0, or -1 if any
- * shift ran out of memory.
+ * Solve all s shifts with the shared right-hand side B.  X is n x (s*m) with
+ * X(:, j*m:(j+1)*m) = X_j, G is p x (s*m) likewise (G_j = C X_j; NaN for a
+ * singular shift); status (length s) is per shift.  nthreads <= 0 uses the
+ * OpenMP default.  Returns 0, or -1 if any shift ran out of memory.
  */
 int oracle_solve(int64_t n, int64_t m, int64_t p,
                  const double *A, int64_t lda,
@@ -192,7 +149,7 @@ int oracle_solve(int64_t n, int64_t m, int64_t p,
                  int64_t s, const double *shifts_ri,
                  double *X_ri, int64_t ldx,
                  double *G_ri, int64_t ldg,
-                 double *eta, int32_t *status, int nthreads)
+                 int32_t *status, int nthreads)
 {
     const zc *shifts = (const zc *)shifts_ri;
     zc *X = (zc *)X_ri;
@@ -205,9 +162,46 @@ int oracle_solve(int64_t n, int64_t m, int64_t p,
 #endif
 #pragma omp parallel for schedule(dynamic, 1) reduction(min : rc)
     for (int64_t j = 0; j < s; ++j) {
-        int st = solve_one(n, m, p, A, lda, B, ldb, C, ldc, shifts[j],
-                           X + j * m * ldx, ldx, G + j * m * ldg, ldg,
-                           eta ? eta + j : NULL);
+        zc *Xj = X + j * m * ldx, *Gj = G + j * m * ldg;
+        int st = solve_one(n, m, A, lda, 0, B, ldb, NULL, 0, shifts[j], Xj, ldx);
+        status[j] = st < 0 ? -1 : st;
+        if (st < 0) rc = -1;
+        /* G_j = C X_j (NaN columns stay NaN) */
+        for (int64_t c = 0; c < m; ++c)
+            for (int64_t i = 0; i < p; ++i) {
+                zc acc = 0.0;
+                for (int64_t k = 0; k < n; ++k) acc += C[i + k * ldc] * Xj[k + c * ldx];
+                Gj[i + c * ldg] = acc;
+            }
+    }
+    return rc;
+}
+
+/*
+ * Per-shift right-hand sides: op(A - sigma_j I) X_j = F_j for j = 0..s-1,
+ * with op the identity (trans = 0) or the transpose (trans = 1).  F is
+ * n x (s*r) complex with F(:, j*r:(j+1)*r) = F_j (ld ldf); X likewise (ld
+ * ldx).  status as for oracle_solve.
+ */
+int oracle_solve_rhs(int64_t n, const double *A, int64_t lda, int trans,
+                     int64_t s, const double *shifts_ri, int64_t r,
+                     const double *F_ri, int64_t ldf,
+                     double *X_ri, int64_t ldx,
+                     int32_t *status, int nthreads)
+{
+    const zc *shifts = (const zc *)shifts_ri;
+    const zc *F = (const zc *)F_ri;
+    zc *X = (zc *)X_ri;
+    int rc = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : rc)
+    for (int64_t j = 0; j < s; ++j) {
+        int st = solve_one(n, r, A, lda, trans != 0, NULL, 0, F + j * r * ldf, ldf, shifts[j],
+                           X + j * r * ldx, ldx);
         status[j] = st < 0 ? -1 : st;
         if (st < 0) rc = -1;
     }

@@ -14,18 +14,22 @@ from __future__ import annotations
 
 import dataclasses
 
-from ._lib import (SHS_MAX_M, SHS_MODE_FP32_REFINE, SHS_MODE_FP64, SHS_OUT_ETA, SHS_OUT_G, SHS_OUT_X,
-                   SHS_STATUS_FALLBACK, SHS_STATUS_NONFINITE, SHS_STATUS_NOT_CONVERGED, SHS_STATUS_OK,
-                   SHS_STATUS_SINGULAR, ShsError, library, shs_apply_q, shs_destroy, shs_get_reduced,
-                   shs_info, shs_last_timings, shs_reduce, shs_server_create, shs_server_destroy,
-                   shs_server_latency, shs_server_poll, shs_server_register, shs_server_stats, shs_server_submit,
+from ._lib import (SHS_ERR_CANCELLED, SHS_ERR_STATE, SHS_MAX_M, SHS_MODE_FP32_REFINE, SHS_MODE_FP64, SHS_OUT_ETA,
+                   SHS_OUT_G, SHS_OUT_X, SHS_REQ_CANCELLED, SHS_REQ_DONE, SHS_REQ_FAILED, SHS_REQ_QUEUED,
+                   SHS_REQ_RUNNING, SHS_STATUS_FALLBACK, SHS_STATUS_NONFINITE, SHS_STATUS_NOT_CONVERGED,
+                   SHS_STATUS_OK, SHS_STATUS_SINGULAR, ShsError, library, shs_apply_q, shs_destroy,
+                   shs_get_reduced, shs_info, shs_last_timings, shs_reduce, shs_server_cancel, shs_server_clock,
+                   shs_server_create, shs_server_destroy, shs_server_latency, shs_server_pause, shs_server_poll,
+                   shs_server_register, shs_server_stats, shs_server_submit, shs_server_submit_ex,
                    shs_server_wait, shs_set_timing, shs_solve, shs_solve_workspace)
 
 __all__ = ["System", "SolveResult", "library", "shs_reduce", "shs_solve", "shs_solve_workspace",
            "shs_apply_q", "shs_get_reduced", "shs_info", "shs_set_timing", "shs_last_timings",
            "shs_destroy", "ShsError", "Server", "Request", "shs_server_create", "shs_server_register",
-           "shs_server_submit", "shs_server_poll", "shs_server_wait", "shs_server_latency", "shs_server_stats",
-           "shs_server_destroy",
+           "shs_server_submit", "shs_server_submit_ex", "shs_server_poll", "shs_server_wait", "shs_server_latency",
+           "shs_server_stats", "shs_server_destroy", "shs_server_cancel", "shs_server_pause", "shs_server_clock",
+           "SHS_REQ_QUEUED", "SHS_REQ_RUNNING", "SHS_REQ_DONE", "SHS_REQ_FAILED", "SHS_REQ_CANCELLED",
+           "SHS_ERR_CANCELLED", "SHS_ERR_STATE",
            "SHS_MODE_FP64", "SHS_MODE_FP32_REFINE", "SHS_OUT_X", "SHS_OUT_G", "SHS_OUT_ETA",
            "SHS_STATUS_OK", "SHS_STATUS_SINGULAR", "SHS_STATUS_NONFINITE", "SHS_STATUS_FALLBACK",
            "SHS_STATUS_NOT_CONVERGED", "SHS_MAX_M"]
@@ -149,7 +153,11 @@ class Server:
         self.systems.append(system)
         return sid
 
-    def submit(self, sys_id, shifts, mode=SHS_MODE_FP64, outputs=SHS_OUT_X | SHS_OUT_G | SHS_OUT_ETA) -> Request:
+    def submit(self, sys_id, shifts, mode=SHS_MODE_FP64, outputs=SHS_OUT_X | SHS_OUT_G | SHS_OUT_ETA,
+               arrival_s=0.0) -> Request:
+        """Queue a request.  Its outputs are allocated on the current stream,
+        and the request's work is ordered after that stream (no device-wide
+        wait); ``arrival_s`` (on :func:`shs_server_clock`) starts its latency."""
         import numpy as np
         import torch
         sysm = self.systems[sys_id]
@@ -161,9 +169,15 @@ class Server:
         eta = (torch.empty(s, dtype=torch.float64, device=sysm.device)
                if (outputs & SHS_OUT_ETA) or mode == SHS_MODE_FP32_REFINE else None)
         status = torch.empty(s, dtype=torch.int32, device=sysm.device)
-        torch.cuda.synchronize()   # the server's streams must see the allocations
-        rid = shs_server_submit(self.handle, sys_id, shifts, X, G, eta, status, mode=mode, outputs=outputs)
+        rid = shs_server_submit_ex(self.handle, sys_id, shifts, X, G, eta, status, mode=mode, outputs=outputs,
+                                   after_stream=torch.cuda.current_stream(), order_after=True, arrival_s=arrival_s)
         return Request(rid, sysm, X, G, eta, status)
+
+    def cancel(self, req: Request):
+        shs_server_cancel(self.handle, req.id)
+
+    def pause(self, paused=True):
+        shs_server_pause(self.handle, paused)
 
     def wait(self, req: Request, timeout_ms=-1.0):
         shs_server_wait(self.handle, req.id, timeout_ms)

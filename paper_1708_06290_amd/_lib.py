@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libshiftsolve.so")
 
-SHS_ABI_VERSION = 1
+SHS_ABI_VERSION = 2
 SHS_MODE_FP64 = 0
 SHS_MODE_FP32_REFINE = 1
 SHS_OUT_X = 1
@@ -25,12 +25,16 @@ SHS_STATUS_NONFINITE = 2
 SHS_STATUS_FALLBACK = 3
 SHS_STATUS_NOT_CONVERGED = 4
 SHS_MAX_M = 16
+SHS_REQ_QUEUED, SHS_REQ_RUNNING, SHS_REQ_DONE, SHS_REQ_FAILED, SHS_REQ_CANCELLED = range(5)
+SHS_ERR_CANCELLED = 7
+SHS_ERR_STATE = 8
 
 EXPORTED = ("shs_reduce", "shs_solve_workspace", "shs_solve", "shs_apply_q", "shs_get_reduced",
             "shs_info", "shs_set_timing", "shs_last_timings", "shs_destroy", "shs_strerror",
             "shs_abi_version", "shs_server_create", "shs_server_register", "shs_server_submit",
             "shs_server_poll", "shs_server_wait", "shs_server_latency", "shs_server_stats",
-            "shs_server_destroy")
+            "shs_server_destroy", "shs_server_submit_ex", "shs_server_cancel", "shs_server_pause",
+            "shs_server_clock")
 
 _lib = None
 
@@ -66,10 +70,15 @@ class _ServerConfig(ctypes.Structure):
 
 
 class _ServerStats(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_int64) for f in ("submitted", "completed", "failed", "queued", "running", "solves",
-                                              "batches", "max_batch_systems")] + \
+    _fields_ = [(f, ctypes.c_int64) for f in ("submitted", "completed", "failed", "cancelled", "queued", "running",
+                                              "solves", "batches", "max_batch_systems", "max_batch_requests")] + \
                [(f, ctypes.c_double) for f in ("p50_ms", "p99_ms", "max_ms", "mean_ms", "busy_s")] + \
                [("peak_bytes", ctypes.c_int64)]
+
+
+class _RequestOpts(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("order_after", ctypes.c_int32), ("after_stream", ctypes.c_void_p),
+                ("arrival_s", ctypes.c_double), ("reserved", ctypes.c_int64 * 4)]
 
 
 class _Config(ctypes.Structure):
@@ -110,6 +119,15 @@ def _load():
     lib.shs_server_submit.argtypes = [vp, ctypes.c_int32, i64, dp, ctypes.c_int, ctypes.c_int, dp, i64, dp, i64,
                                       dp, vp, ctypes.POINTER(ctypes.c_int64)]
     lib.shs_server_submit.restype = ctypes.c_int
+    lib.shs_server_submit_ex.argtypes = [vp, ctypes.c_int32, i64, dp, ctypes.c_int, ctypes.c_int, dp, i64, dp, i64,
+                                         dp, vp, ctypes.POINTER(_RequestOpts), ctypes.POINTER(ctypes.c_int64)]
+    lib.shs_server_submit_ex.restype = ctypes.c_int
+    lib.shs_server_cancel.argtypes = [vp, i64]
+    lib.shs_server_cancel.restype = ctypes.c_int
+    lib.shs_server_pause.argtypes = [vp, ctypes.c_int]
+    lib.shs_server_pause.restype = ctypes.c_int
+    lib.shs_server_clock.argtypes = []
+    lib.shs_server_clock.restype = ctypes.c_double
     lib.shs_server_poll.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_int)]
     lib.shs_server_poll.restype = ctypes.c_int
     lib.shs_server_wait.argtypes = [vp, i64, ctypes.c_double]
@@ -281,6 +299,38 @@ def shs_server_submit(srv, sys_id, shifts_host, X, G, eta, status, mode=SHS_MODE
                                    _ptr(X), ldx, _ptr(G), ldg, _ptr(eta), _ptr(status), ctypes.byref(rid))
     _check("shs_server_submit", rc)
     return rid.value
+
+
+def shs_server_submit_ex(srv, sys_id, shifts_host, X, G, eta, status, mode=SHS_MODE_FP64,
+                         outputs=SHS_OUT_X | SHS_OUT_G, after_stream=None, order_after=True, arrival_s=0.0):
+    """Queue a request whose work is ordered after ``after_stream`` (a torch
+    stream; None = the current stream) and whose latency runs from
+    ``arrival_s`` on the :func:`shs_server_clock` clock (0 = now)."""
+    import numpy as np
+    sh = np.ascontiguousarray(np.asarray(shifts_host, dtype=np.complex128).reshape(-1))
+    opts = _RequestOpts(abi_version=SHS_ABI_VERSION, order_after=1 if order_after else 0,
+                        after_stream=_stream(after_stream) if order_after else None, arrival_s=float(arrival_s))
+    rid = ctypes.c_int64()
+    ldx = X.shape[1] if X is not None else 1
+    ldg = G.shape[1] if G is not None else 1
+    rc = _load().shs_server_submit_ex(srv, sys_id, sh.size, sh.ctypes.data_as(ctypes.c_void_p), mode, outputs,
+                                      _ptr(X), ldx, _ptr(G), ldg, _ptr(eta), _ptr(status), ctypes.byref(opts),
+                                      ctypes.byref(rid))
+    _check("shs_server_submit_ex", rc)
+    return rid.value
+
+
+def shs_server_cancel(srv, req_id):
+    _check("shs_server_cancel", _load().shs_server_cancel(srv, req_id))
+
+
+def shs_server_pause(srv, paused: bool):
+    _check("shs_server_pause", _load().shs_server_pause(srv, 1 if paused else 0))
+
+
+def shs_server_clock() -> float:
+    """The server's steady clock in seconds (for request arrival times)."""
+    return float(_load().shs_server_clock())
 
 
 def shs_server_poll(srv, req_id):

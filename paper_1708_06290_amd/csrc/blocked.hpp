@@ -87,6 +87,7 @@ struct BlkTriArgs {
     double *M2q;               // per work item W x W: composite M2 including this tile
     int gk;                    // 0: bottom tile; k = 1 .. D: k-th tile of a group
     int D;                     // tiles per group; Bm holds D TT + m rows
+    const int *dcount;         // if set, the number of work items is read here (count is an upper bound)
 };
 
 // Block-transform destinations (n_b = TT rows of M1 per tile):
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
     __shared__ T lds_rs[2 * M * M];
     __shared__ T lds_m2[W * W];   // M2_b of a second tile, real form
     const int item = blockIdx.x;
-    if (item >= a.count) return;
+    if (item >= (a.dcount ? *a.dcount : a.count)) return;
     const int sid = a.list ? a.list[item] : item;
     const int lane = threadIdx.x;
     const int n = a.n, t = a.t;
@@ -359,6 +360,7 @@ struct ZupdArgs {
     int64_t ldz;
     const double *shifts;
     const int32_t *list;
+    const int *dcount;         // if set, the number of work items is read here (count is an upper bound)
 };
 
 typedef double zupd_dbl4 __attribute__((ext_vector_type(4)));
@@ -420,6 +422,8 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgs a)
         i0 = a.r0 + (grp * GR + r % rows) * BM;
         j0 = (r / rows) * BN;
     }
+    const int count = a.dcount ? *a.dcount : a.count;
+    if (j0 >= count * W) return;   // uniform: every column of the tile belongs to no listed item
 
     zupd_dbl4 acc[4][4];
 #pragma unroll
@@ -525,10 +529,10 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgs a)
                 double v = acc[mt][nt][r];
                 if (i >= lo - m) {
                     const int w = j / W, q = j % W;
-                    const int sid = w < a.count ? (a.list ? a.list[w] : w) : 0;
+                    const int sid = w < count ? (a.list ? a.list[w] : w) : 0;
                     const double sr = a.shifts[2 * sid], si = a.shifts[2 * sid + 1];
                     // a non-finite sigma has a zero transform and keeps Z zero
-                    if (w < a.count && q < 2 * m && isfinite(sr) && isfinite(si)) {
+                    if (w < count && q < 2 * m && isfinite(sr) && isfinite(si)) {
                         const int c = q < m ? q : q - m;
                         const int p = i - (lo - m);
                         const double ur = a.Bm[(int64_t)p * a.ldb + w * W + c];

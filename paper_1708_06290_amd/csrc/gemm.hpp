@@ -13,9 +13,114 @@
 // the result does not depend on scheduling.
 #pragma once
 
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
 #include "common.hpp"
 
 namespace shs {
+
+// Grid of one GEMM launch: gx x gy tiles of BM x BN, K split into nsplit
+// chunks of kchunk (a multiple of 16).  K is split when the tile grid alone
+// cannot fill the chip: aim at ~1024 workgroups, chunks of at least 128,
+// partials within the workspace (part_elems doubles).
+struct GemmPlan {
+    int gx, gy, nsplit, kchunk;
+};
+
+inline GemmPlan gemm_plan(int M, int N, int K, int BM, int BN, bool has_part, size_t part_elems)
+{
+    GemmPlan g;
+    g.gx = (M + BM - 1) / BM;
+    g.gy = (N + BN - 1) / BN;
+    g.nsplit = 1;
+    const int64_t tiles = (int64_t)g.gx * g.gy;
+    if (tiles < 512 && K >= 256 && has_part) {
+        int64_t want = std::min<int64_t>(1024 / tiles, K / 128);
+        const int64_t room = (int64_t)(part_elems / ((size_t)M * N));
+        g.nsplit = (int)std::max<int64_t>(1, std::min(want, room));
+    }
+    g.kchunk = 16;
+    if (K > 0) {
+        g.kchunk = ((K + g.nsplit - 1) / g.nsplit + 15) / 16 * 16;
+        g.nsplit = (K + g.kchunk - 1) / g.kchunk;
+    }
+    return g;
+}
+
+// Tile shape gemm_shape picks for an M x N result.
+inline void gemm_tile(int M, int N, int *BM, int *BN)
+{
+    if (N <= 16 && M <= 64) { *BM = 64; *BN = 16; }
+    else if (N <= 16) { *BM = 256; *BN = 16; }
+    else if (M <= 16) { *BM = 16; *BN = 256; }
+    else if (M <= 64) { *BM = 64; *BN = 128; }
+    else { *BM = 128; *BN = 128; }
+}
+
+// Dry run of a sequence of launches: instead of launching, every GEMM is
+// checked against the device regions registered here (base address and
+// size in doubles): the extent each operand is read or written over, the
+// split-K partials against the workspace, the grid against the launch
+// limits, and that the result does not overlap an operand.  Used on the
+// host to validate a whole launch plan without a GPU.
+struct LaunchCheck {
+    struct Region { uintptr_t lo, hi; const char *name; };
+    std::vector<Region> regions;
+    int64_t launches = 0, violations = 0;
+    char first[256] = {0};
+
+    void add(const void *p, size_t elems, const char *name)
+    {
+        const uintptr_t lo = (uintptr_t)p;
+        regions.push_back({lo, lo + elems * sizeof(double), name});
+    }
+    void fail(const char *what, int M, int N, int K)
+    {
+        if (violations++ == 0) snprintf(first, sizeof(first), "%s (M=%d N=%d K=%d)", what, M, N, K);
+    }
+    // [p, p + last] (last in doubles, inclusive) inside one region
+    const Region *inside(const double *p, int64_t last) const
+    {
+        const uintptr_t lo = (uintptr_t)p, hi = lo + (uintptr_t)(last + 1) * sizeof(double);
+        for (const auto &r : regions)
+            if (lo >= r.lo && hi <= r.hi) return &r;
+        return nullptr;
+    }
+    void gemm(bool ta, bool tb, int M, int N, int K, const double *A, int64_t lda, const double *B, int64_t ldb,
+              const double *C, int64_t ldc, const double *part, size_t part_elems)
+    {
+        ++launches;
+        int BM = 0, BN = 0;
+        gemm_tile(M, N, &BM, &BN);
+        const GemmPlan g = gemm_plan(M, N, K, BM, BN, part != nullptr, part_elems);
+        if (g.gx < 1 || g.gy < 1 || g.gy > 65535 || g.nsplit < 1 || g.nsplit > 65535) fail("grid", M, N, K);
+        if ((int64_t)g.nsplit * g.kchunk < K || (int64_t)(g.nsplit - 1) * g.kchunk >= std::max(K, 1))
+            fail("k split", M, N, K);
+        if (g.nsplit > 1 && (!part || (size_t)g.nsplit * M * N > part_elems)) fail("split-K partials", M, N, K);
+        // extents: op(A) is M x K, op(B) is K x N, C is M x N (column-major)
+        if (K > 0) {
+            if ((ta ? lda < K : lda < M) || !inside(A, ta ? (int64_t)(M - 1) * lda + K - 1
+                                                           : (int64_t)(K - 1) * lda + M - 1))
+                fail("A extent", M, N, K);
+            if ((tb ? ldb < N : ldb < K) || !inside(B, tb ? (int64_t)(K - 1) * ldb + N - 1
+                                                           : (int64_t)(N - 1) * ldb + K - 1))
+                fail("B extent", M, N, K);
+        }
+        const int64_t clast = (int64_t)(N - 1) * ldc + M - 1;
+        if (ldc < M || !inside(C, clast)) fail("C extent", M, N, K);
+        auto overlap = [&](const double *X, int64_t xlast) {
+            const uintptr_t a0 = (uintptr_t)C, a1 = a0 + (uintptr_t)(clast + 1) * 8;
+            const uintptr_t b0 = (uintptr_t)X, b1 = b0 + (uintptr_t)(xlast + 1) * 8;
+            return a0 < b1 && b0 < a1;
+        };
+        if (K > 0 && (overlap(A, ta ? (int64_t)(M - 1) * lda + K - 1 : (int64_t)(K - 1) * lda + M - 1) ||
+                      overlap(B, tb ? (int64_t)(K - 1) * ldb + N - 1 : (int64_t)(N - 1) * ldb + K - 1)))
+            fail("result overlaps an operand", M, N, K);
+        if (g.nsplit > 1 && part && overlap(part, (int64_t)g.nsplit * M * N - 1)) fail("partials overlap C", M, N, K);
+    }
+};
 
 typedef double gemm_dbl4 __attribute__((ext_vector_type(4)));
 
@@ -137,21 +242,8 @@ inline void gemm_launch(int M, int N, int K, double alpha, const double *A, int6
                         int64_t ldb, double *C, int64_t ldc, int acc, double *part, size_t part_elems,
                         hipStream_t st)
 {
-    const int gx = (M + BM - 1) / BM, gy = (N + BN - 1) / BN;
-    // split K when the tile grid alone cannot fill the chip: aim at ~1024
-    // workgroups, chunks of at least 128, partials within the workspace
-    int nsplit = 1;
-    const int64_t tiles = (int64_t)gx * gy;
-    if (tiles < 512 && K >= 256 && part != nullptr) {
-        int64_t want = std::min<int64_t>(1024 / tiles, K / 128);
-        const int64_t room = (int64_t)(part_elems / ((size_t)M * N));
-        nsplit = (int)std::max<int64_t>(1, std::min(want, room));
-    }
-    int kchunk = 16;
-    if (K > 0) {
-        kchunk = ((K + nsplit - 1) / nsplit + 15) / 16 * 16;
-        nsplit = (K + kchunk - 1) / kchunk;
-    }
+    const GemmPlan g = gemm_plan(M, N, K, BM, BN, part != nullptr, part_elems);
+    const int gx = g.gx, gy = g.gy, nsplit = g.nsplit, kchunk = g.kchunk;
     hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, BM, BN, WM>), dim3(gx, gy, nsplit), dim3(256), 0, st, M, N, K,
                        kchunk, alpha, A, lda, B, ldb, C, ldc, acc, part);
     if (nsplit > 1) {
@@ -166,13 +258,15 @@ inline void gemm_shape(int M, int N, int K, double alpha, const double *A, int64
                        int64_t ldb, double *C, int64_t ldc, int acc, double *part, size_t part_elems,
                        hipStream_t st)
 {
-    if (N <= 16 && M <= 64)
+    int BM = 0, BN = 0;
+    gemm_tile(M, N, &BM, &BN);
+    if (BM == 64 && BN == 16)
         gemm_launch<TA, TB, 64, 16, 4>(M, N, K, alpha, A, lda, B, ldb, C, ldc, acc, part, part_elems, st);
-    else if (N <= 16)
+    else if (BM == 256)
         gemm_launch<TA, TB, 256, 16, 4>(M, N, K, alpha, A, lda, B, ldb, C, ldc, acc, part, part_elems, st);
-    else if (M <= 16)
+    else if (BM == 16)
         gemm_launch<TA, TB, 16, 256, 1>(M, N, K, alpha, A, lda, B, ldb, C, ldc, acc, part, part_elems, st);
-    else if (M <= 64)
+    else if (BM == 64)
         gemm_launch<TA, TB, 64, 128, 4>(M, N, K, alpha, A, lda, B, ldb, C, ldc, acc, part, part_elems, st);
     else
         gemm_launch<TA, TB, 128, 128, 2>(M, N, K, alpha, A, lda, B, ldb, C, ldc, acc, part, part_elems, st);
@@ -183,9 +277,13 @@ inline void gemm_shape(int M, int N, int K, double alpha, const double *A, int64
 // null) is the split-K workspace; it must not overlap the operands.
 inline hipError_t gemm_f64(bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int64_t lda,
                            const double *B, int64_t ldb, double *C, int64_t ldc, bool accumulate, double *part,
-                           size_t part_elems, hipStream_t st)
+                           size_t part_elems, hipStream_t st, LaunchCheck *chk = nullptr)
 {
     if (M <= 0 || N <= 0 || (K <= 0 && accumulate)) return hipSuccess;
+    if (chk) {   // dry run: validate, launch nothing
+        chk->gemm(ta, tb, M, N, K, A, lda, B, ldb, C, ldc, part, part_elems);
+        return hipSuccess;
+    }
     const int acc = accumulate ? 1 : 0;
     if (!ta && !tb) gemm_shape<false, false>(M, N, K, alpha, A, lda, B, ldb, C, ldc, acc, part, part_elems, st);
     else if (!ta && tb) gemm_shape<false, true>(M, N, K, alpha, A, lda, B, ldb, C, ldc, acc, part, part_elems, st);

@@ -33,8 +33,9 @@ struct shs_handle {
     struct Mark { int phase; int64_t shifts; hipEvent_t a, b; };
     std::vector<Mark> marks;
     std::vector<hipEvent_t> pool;
-    int64_t refine_iterations = 0, fallback_shifts = 0;
+    bool last_mixed = false;   // the last timed solve ran the mixed mode
     double tile_flops = 0.0, update_flops = 0.0;   // algorithmic flops of the blocked sweep's launches
+    long long *dstats = nullptr;   // device counters of the mixed mode's last timed solve (3 values)
 };
 
 enum { PH_SWEEP = 0, PH_QSTAR, PH_RESIDUAL, PH_SWEEP32, PH_SWEEP32D, PH_OTHER, PH_TILE, PH_UPDATE, PH_COUNT };
@@ -42,11 +43,12 @@ enum { PH_SWEEP = 0, PH_QSTAR, PH_RESIDUAL, PH_SWEEP32, PH_SWEEP32D, PH_OTHER, P
 namespace shs {
 
 // FP64 residual R - (H X - sigma X) and backward error of the listed shifts
-// (dlist == nullptr: shifts 0 .. s_list-1); Res optional; resmax/xmax are
-// per-column scratch of m * s_total entries.
-hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const double *shifts, const double *X,
-                   int64_t ldx, double *Res, unsigned long long *resmax, unsigned long long *xmax, double *eta,
-                   int32_t *status, int64_t s_total, double *Xt, hipStream_t st);
+// (dlist == nullptr: shifts 0 .. s_list-1; dcount set: the list's length is
+// read on the device, s_list is then an upper bound); Res optional;
+// resmax/xmax are per-column scratch of m * s_total entries.
+hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const int *dcount, const double *shifts,
+                   const double *X, int64_t ldx, double *Res, unsigned long long *resmax, unsigned long long *xmax,
+                   double *eta, int32_t *status, int64_t s_total, double *Xt, hipStream_t st);
 
 // G(:, j*m + c) = Ct X(:, j*m + c) for shifts 0 .. s-1.
 hipError_t g_eval(shs_handle *h, int64_t s, const double *X, int64_t ldx, double *G, int64_t ldg, hipStream_t st);

@@ -43,6 +43,7 @@ void free_handle(shs_handle *h)
     hipFree(h->sgn);
     hipFree(h->offrow);
     hipFree(h->diag);
+    hipFree(h->dstats);
     delete h;
 }
 
@@ -119,6 +120,7 @@ bool geo(bool fp32, int64_t n, int64_t m, bool dense, Geo *out)
 struct Layout {
     size_t refl64 = 0, y64 = 0, x = 0, resmax = 0, xmax = 0, list = 0;
     size_t refl32 = 0, y32 = 0, e32 = 0, yd32 = 0, res = 0, scale = 0, eta_prev = 0, status2 = 0;
+    size_t list2 = 0, fblist = 0, cnt = 0;   // mixed mode: device-side shift lists and their counts
     // blocked FP64 sweep (FP64 mode): carried columns, block transforms
     bool blocked = false;
     size_t zb = 0, bm = 0, m2 = 0, m2p = 0, m2q = 0;
@@ -147,7 +149,16 @@ bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
     L->list = take(sizeof(int32_t) * s);
     L->status2 = take(sizeof(int32_t) * s);
     L->xt = take(sizeof(double) * residual_pack_rows(n) * residual_pack_ld(m * s));
-    if (mode == SHS_MODE_FP64) {
+    if (mode == SHS_MODE_FP32_REFINE) {
+        L->list2 = take(sizeof(int32_t) * s);
+        L->fblist = take(sizeof(int32_t) * s);
+        L->cnt = take(sizeof(int) * 4);
+    }
+    // the mixed form's refinement buffers and the blocked FP64 sweep's
+    // buffers (its fallback) are never live together: they share one region
+    const size_t region = off;
+    size_t end_blk = off, end_mix = off;
+    {
         int tr = 0, w = 0;
         if (!blk_geometry((int)m, &tr, &w)) return false;
         L->blocked = true;
@@ -159,8 +170,10 @@ bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
         L->m2 = take(sizeof(double) * (L->blk_cols / w) * w * w);
         L->m2p = take(sizeof(double) * (L->blk_cols / w) * w * w);
         L->m2q = take(sizeof(double) * (L->blk_cols / w) * w * w);
+        end_blk = off;
     }
     if (mode == SHS_MODE_FP32_REFINE) {
+        off = region;
         if (!geo(true, n, m, false, &g32s) || !geo(true, n, m, true, &g32d)) return false;
         L->refl32 = take(sizeof(float) * std::max(g32s.stride, g32d.stride) * s);
         L->y32 = take(sizeof(float) * 2 * m * m * s);
@@ -169,21 +182,23 @@ bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
         L->res = take(sizeof(double) * 2 * n * m * s);
         L->scale = take(sizeof(double) * s);
         L->eta_prev = take(sizeof(double) * s);
+        end_mix = off;
     }
-    L->total = off;
+    L->total = std::max(end_blk, end_mix);
     return true;
 }
 
 template <typename T>
 inline T *at(void *base, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(base) + off); }
 
-// E32(:, sid*m + c) = Res(:, sid*m + c) / scale[sid], scale = 2^ceil(log2(max |Res_sid|)).
-__global__ __launch_bounds__(256) void scale_residual_kernel(int n, int m, int count, const int32_t *list,
+// E32(:, sid*m + c) = Res(:, sid*m + c) / scale[sid], scale = 2^ceil(log2(max |Res_sid|)),
+// for the listed shifts (item = blockIdx.x < *dcount).
+__global__ __launch_bounds__(256) void scale_residual_kernel(int n, int m, const int *dcount, const int32_t *list,
                                                              const double *Res, const unsigned long long *resmax,
                                                              double *scale, float *E32)
 {
-    const int item = blockIdx.y;
-    if (item >= count) return;
+    const int item = blockIdx.x;
+    if (item >= *dcount) return;
     const int sid = list[item];
     double mx = 0.0;
     for (int c = 0; c < m; ++c) {
@@ -191,10 +206,10 @@ __global__ __launch_bounds__(256) void scale_residual_kernel(int n, int m, int c
         mx = v > mx ? v : mx;
     }
     const double sc = mx > 0.0 ? exp2(ceil(log2(mx))) : 1.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) scale[sid] = sc;
+    if (blockIdx.y == 0 && threadIdx.x == 0) scale[sid] = sc;
     const double inv = 1.0 / sc;
     const int64_t total = (int64_t)n * m;
-    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
+    for (int64_t idx = (int64_t)blockIdx.y * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.y * 256) {
         const int64_t c = idx / n, i = idx % n;
         const double *pr = Res + (((int64_t)sid * m + c) * n + i) * 2;
         float *pe = E32 + ((int64_t)sid * n * m + c * n + i) * 2;
@@ -203,19 +218,109 @@ __global__ __launch_bounds__(256) void scale_residual_kernel(int n, int m, int c
     }
 }
 
-__global__ void fill_status_kernel(int count, const int32_t *list, const int32_t *src, int32_t *dst, int code)
+// Mixed mode, device-side bookkeeping (no host synchronisation inside a
+// solve).  cnt[0] and cnt[1] are the lengths of the two alternating lists of
+// shifts still being refined, cnt[2] that of the fallback list; stats (if
+// set, timing only) counts correction rounds, fallback shifts and the
+// shift-solves of the correction sweeps.
+__global__ void mixed_init_kernel(int s, int32_t *list, double *eta_prev, int *cnt, long long *stats)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= count) return;
-    const int sid = list ? list[i] : i;
-    const int st = src[sid];
-    dst[sid] = (st == 0) ? code : st;
+    if (i < s) {
+        list[i] = i;
+        eta_prev[i] = __longlong_as_double(0x7ff0000000000000LL);   // +inf
+    }
+    if (i == 0) {
+        cnt[0] = s;
+        cnt[1] = 0;
+        cnt[2] = 0;
+        if (stats) stats[0] = stats[1] = stats[2] = 0;
+    }
+}
+
+// After the residual of refinement round `it`: every listed shift with
+// eta <= tol is done (status OK); one whose eta is NaN, did not at least
+// halve since the previous round, or has used max_iter corrections goes to
+// the fallback list; the others go to the next list.  One workgroup keeps
+// both lists in the order of the input list (block-wide prefix sums).
+__global__ __launch_bounds__(1024) void mixed_select_kernel(int it, int max_iter, double tol, const int32_t *in,
+                                                            const int *cin, int32_t *out, int *cout, int32_t *fb,
+                                                            int *cfb, const double *eta, double *eta_prev,
+                                                            int32_t *status, long long *stats)
+{
+    __shared__ int sn[1024], sf[1024];
+    __shared__ int base_n, base_f;
+    const int t = threadIdx.x;
+    const int count = *cin;
+    if (t == 0) {
+        base_n = 0;
+        base_f = *cfb;
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < count; c0 += 1024) {
+        const int item = c0 + t;
+        int kind = 0;   // 0 done or idle, 1 next, 2 fallback
+        int sid = 0;
+        if (item < count) {
+            sid = in[item];
+            const double v = eta[sid];
+            if (v <= tol) {
+                status[sid] = SHS_STATUS_OK;
+            } else if (!(v == v) || it >= max_iter || !(v <= 0.5 * eta_prev[sid])) {
+                kind = 2;
+            } else {
+                eta_prev[sid] = v;
+                kind = 1;
+            }
+        }
+        sn[t] = kind == 1;
+        sf[t] = kind == 2;
+        __syncthreads();
+        // inclusive prefix sums (Hillis-Steele)
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int an = t >= d ? sn[t - d] : 0, af = t >= d ? sf[t - d] : 0;
+            __syncthreads();
+            sn[t] += an;
+            sf[t] += af;
+            __syncthreads();
+        }
+        if (kind == 1) out[base_n + sn[t] - 1] = sid;
+        if (kind == 2) fb[base_f + sf[t] - 1] = sid;
+        __syncthreads();
+        if (t == 0) {
+            base_n += sn[1023];
+            base_f += sf[1023];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        *cout = base_n;
+        *cfb = base_f;
+        if (stats) {
+            if (base_n > 0) stats[0] += 1;
+            stats[1] = base_f;
+            stats[2] += base_n;
+        }
+    }
+}
+
+// Final status of the shifts the FP64 sweep recomputed: its own status if
+// not OK (singular, non-finite), else FALLBACK when its eta meets tol and
+// NOT_CONVERGED otherwise.
+__global__ void mixed_final_kernel(const int *cfb, const int32_t *fb, const int32_t *st64, const double *eta,
+                                   double tol, int32_t *status)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= *cfb) return;
+    const int sid = fb[i];
+    const int st = st64[sid];
+    status[sid] = st != SHS_STATUS_OK ? st : (eta[sid] <= tol ? SHS_STATUS_FALLBACK : SHS_STATUS_NOT_CONVERGED);
 }
 
 // Blocked FP64 sweep of the listed shifts: per row tile (bottom to top) the
 // per-shift tile kernel, then the all-shift update of the rows above.
-hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, const double *shifts, void *work,
-                         const Layout &L, const SweepArgs<double> &sa, hipStream_t st)
+hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, const int *dcount, const double *shifts,
+                         void *work, const Layout &L, const SweepArgs<double> &sa, hipStream_t st)
 {
     const int n = (int)h->n, m = (int)h->m;
     int tr = 0, w = 0;
@@ -257,6 +362,7 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     ta.ldb = ncols;
     ta.M2 = M2;
     ta.D = kBlkGroup;
+    ta.dcount = dcount;
     ZupdArgs za{};
     za.m = m;
     za.n = n;
@@ -271,6 +377,7 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     za.ldz = n;
     za.shifts = shifts;
     za.list = dlist;
+    za.dcount = dcount;
     // bottom tile: all rows above it at once (K = n_b + m, no Z yet); then
     // groups of kBlkGroup tiles: after the k-th, the next tile's rows get the
     // group's composite (K = k n_b); after the last, all rows above do
@@ -287,7 +394,7 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
             PhaseScope ps(h, PH_TILE, count, st);
             if (!launch_blk_tri(m, ta, st)) return hipErrorInvalidValue;
         }
-        if (h->timing) {   // timing state is only touched when enabled
+        if (h->timing && !dcount) {   // timing state is only touched when enabled (flops: host-known counts only)
             // steps: (16m+4) flops per row above the pivot in the tile; the
             // block transform: n_b reflectors on m columns of length m+1; a
             // group's k-th tile: its older composite rows and M2 times 2m x 2m
@@ -328,7 +435,7 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
         }
         // H(rows, K columns) times 2m real columns per shift, plus z times a
         // 2m x 2m matrix when carried columns are read
-        if (h->timing)
+        if (h->timing && !dcount)
             h->update_flops +=
                 (2.0 * (za.lo - za.r0) * za.K * 2 * m + (za.has_zin ? 2.0 * (za.lo - za.r0) * 4.0 * m * m : 0.0)) *
                 (double)count;
@@ -336,9 +443,10 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     return hipGetLastError();
 }
 
-// FP64 sweep + Q* pass for the listed shifts into X.
-hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const double *shifts, void *work,
-                      const Layout &L, double *X, int64_t ldx, int32_t *status, hipStream_t st)
+// FP64 sweep + Q* pass for the listed shifts into X (dcount: the list's
+// length on the device, count then an upper bound).
+hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const int *dcount, const double *shifts,
+                      void *work, const Layout &L, double *X, int64_t ldx, int32_t *status, hipStream_t st)
 {
     const int64_t n = h->n, m = h->m;
     Geo g;
@@ -356,8 +464,9 @@ hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const 
     sa.Y = at<double>(work, L.y64);
     sa.y_stride = 2 * m * m;
     sa.status = status;
+    sa.dcount = dcount;
     if (L.blocked) {
-        hipError_t e = sweep_blocked(h, count, dlist, shifts, work, L, sa, st);
+        hipError_t e = sweep_blocked(h, count, dlist, dcount, shifts, work, L, sa, st);
         if (e != hipSuccess) return e;
     } else {
         PhaseScope ps(h, PH_SWEEP, count, st);
@@ -378,6 +487,7 @@ hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const 
     qa.ldx = ldx;
     qa.accumulate = 0;
     qa.scale = nullptr;
+    qa.dcount = dcount;
     {
         PhaseScope ps(h, PH_QSTAR, count, st);
         if (!launch_qstar((int)m, false, qa, st)) return hipErrorInvalidValue;
@@ -390,9 +500,9 @@ hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const 
 namespace shs {
 
 // residual + eta for the listed shifts; Res optional.
-hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const double *shifts, const double *X,
-                   int64_t ldx, double *Res, unsigned long long *resmax, unsigned long long *xmax, double *eta,
-                   int32_t *status, int64_t s_total, double *Xt, hipStream_t st)
+hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const int *dcount, const double *shifts,
+                   const double *X, int64_t ldx, double *Res, unsigned long long *resmax, unsigned long long *xmax,
+                   double *eta, int32_t *status, int64_t s_total, double *Xt, hipStream_t st)
 {
     const int64_t n = h->n, m = h->m;
     // timed phases: the residual GEMM alone; clearing, packing and eta count
@@ -419,6 +529,7 @@ hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const do
     ra.ldr = n;
     ra.resmax = resmax;
     ra.xmax = xmax;
+    ra.dcount = dcount;
     if (s_list <= 0) return hipGetLastError();
     // what the direct-to-LDS loads assume: 16-byte aligned pairs of rows
     if (n < 2 || h->ldh & 1 || ((uintptr_t)h->H | (uintptr_t)Xt) & 15) return hipErrorInvalidValue;
@@ -431,7 +542,7 @@ hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const do
                            st, ra);
     }
     PhaseScope ps1(h, PH_OTHER, s_list, st);
-    hipLaunchKernelGGL(eta_kernel, dim3((unsigned)s_list), dim3(256), 0, st, (int)n, (int)m, (int)s_list, dlist,
+    hipLaunchKernelGGL(eta_kernel, dim3((unsigned)s_list), dim3(256), 0, st, (int)n, (int)m, (int)s_list, dcount, dlist,
                        shifts, (const double *)h->offrow, (const double *)h->diag, (const double *)h->rcolmax,
                        (const unsigned long long *)resmax, (const unsigned long long *)xmax, eta, status);
     return hipGetLastError();
@@ -504,7 +615,7 @@ constexpr size_t kReducePart = (size_t)1 << 22;   // split-K workspace of the re
 //   then the trailing columns c >= z + b: right A -= Y V^T, left A -= V T^T V^T A,
 //   and C <- C (I - V T V^T).  Y = A V T always refers to the panel-start A;
 //   the columns it reads (>= j0 + m) are still untouched when it is formed.
-hipError_t reduce_blocked(shs_handle *h, double *work, hipStream_t st)
+hipError_t reduce_blocked(shs_handle *h, double *work, hipStream_t st, LaunchCheck *chk = nullptr)
 {
     const int n = (int)h->n, m = (int)h->m, p = (int)h->p;
     const int b = std::max(m, (64 / m) * m);
@@ -524,20 +635,22 @@ hipError_t reduce_blocked(shs_handle *h, double *work, hipStream_t st)
     double *part = taus + b;                            // split-K partials
     const int ldp = std::max(1, p);
     hipError_t e = hipSuccess;
-#define GEMM(...)                                    \
-    do {                                             \
-        e = gemm_f64(__VA_ARGS__, part, kReducePart, st); \
-        if (e != hipSuccess) return e;               \
+#define GEMM(...)                                         \
+    do {                                                  \
+        e = gemm_f64(__VA_ARGS__, part, kReducePart, st, chk); \
+        if (e != hipSuccess) return e;                    \
     } while (0)
     const int nref = n - m - 1;   // columns that get a reflector
     for (int z = 0; z < nref; z += b) {
         const int bz = std::min(b, nref - z);
         const int r_lo = z + m, L = n - r_lo;
         // rows above each vector's first row are read by the GEMMs as zeros
-        e = hipMemsetAsync(Vp, 0, sizeof(double) * n * b, st);
-        if (e != hipSuccess) return e;
-        e = hipMemsetAsync(Tp, 0, sizeof(double) * b * b, st);
-        if (e != hipSuccess) return e;
+        if (!chk) {
+            e = hipMemsetAsync(Vp, 0, sizeof(double) * n * b, st);
+            if (e != hipSuccess) return e;
+            e = hipMemsetAsync(Tp, 0, sizeof(double) * b * b, st);
+            if (e != hipSuccess) return e;
+        }
         for (int q0 = 0; q0 < bz; q0 += m) {
             const int mb = std::min(m, bz - q0);
             const int j0 = z + q0;
@@ -551,10 +664,12 @@ hipError_t reduce_blocked(shs_handle *h, double *work, hipStream_t st)
                 GEMM(false, false, L, mb, q0, -1.0, Vp + r_lo, n, U, b, Acols + r_lo, ldh, true);
             }
             // 3. this mini-block's reflectors and T block
-            hipLaunchKernelGGL(miniblock_kernel, dim3(1), dim3(1024), 0, st, n, m, r_lo, j0, mb, q0, H, ldh, Vp,
-                               taus, Tp, b);
-            e = hipGetLastError();
-            if (e != hipSuccess) return e;
+            if (!chk) {
+                hipLaunchKernelGGL(miniblock_kernel, dim3(1), dim3(1024), 0, st, n, m, r_lo, j0, mb, q0, H, ldh, Vp,
+                                   taus, Tp, b);
+                e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
             const double *Vnew = Vp + (int64_t)q0 * n;
             if (q0 > 0) {
                 // 4. S = V_old^T V_new; T12 = -T_old S T_new
@@ -583,12 +698,164 @@ hipError_t reduce_blocked(shs_handle *h, double *work, hipStream_t st)
             GEMM(false, true, p, L, bz, -1.0, CVT, ldp, Vp + r_lo, n, h->Ct + (int64_t)r_lo * h->ldct, h->ldct, true);
         }
         // keep the reflectors for Q (apply_q): reflector m + z + q
+        if (chk) {
+            if (!chk->inside(h->V + (int64_t)(m + z) * n, (int64_t)n * bz - 1) ||
+                !chk->inside(h->tauv + m + z, bz - 1))
+                chk->fail("reflector copy", n, bz, 0);
+            continue;
+        }
         e = hipMemcpyAsync(h->V + (int64_t)(m + z) * n, Vp, sizeof(double) * n * bz, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;
         e = hipMemcpyAsync(h->tauv + m + z, taus, sizeof(double) * bz, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;
     }
 #undef GEMM
+    return chk ? hipSuccess : hipGetLastError();
+}
+
+// Mixed precision (complex FP32 sweep + FP64 iterative refinement), all on
+// the stream: the shifts still being refined, and those that fall back to
+// the FP64 sweep, are kept in device lists whose lengths the kernels read on
+// the device, so the host never waits.  Every round launches its kernels for
+// up to s shifts; launches past a list's length exit at once.
+//   X = Q* (FP32 sweep of all shifts)
+//   for it = 0 .. max_iter:
+//       eta of the listed shifts (FP64 residual GEMM); split the list into
+//       done / next / fallback (mixed_select_kernel); stop at it = max_iter
+//       correction of the next list: (H - sigma I) D = Res / scale in FP32
+//       (dense right-hand side), X += scale D
+//   FP64 (blocked) sweep and eta of the fallback list; their status.
+hipError_t solve_mixed(shs_handle *h, int64_t s, const double *shifts, double tol, int max_iter, void *work,
+                       const Layout &L, double *Xw, int64_t ldxw, double *eta, int32_t *status, hipStream_t st)
+{
+    const int64_t n = h->n, m = h->m;
+    Geo g32s, g32d;
+    geo(true, n, m, false, &g32s);
+    geo(true, n, m, true, &g32d);
+    int32_t *lists[2] = {at<int32_t>(work, L.list), at<int32_t>(work, L.list2)};
+    int32_t *fbl = at<int32_t>(work, L.fblist);
+    int *cnt = at<int>(work, L.cnt);
+    int32_t *st2 = at<int32_t>(work, L.status2);
+    double *Res = at<double>(work, L.res);
+    long long *stats = h->timing ? h->dstats : nullptr;
+    hipError_t e = hipSuccess;
+    {
+        PhaseScope ps(h, PH_OTHER, s, st);
+        hipLaunchKernelGGL(mixed_init_kernel, dim3(cdiv(s, 256)), dim3(256), 0, st, (int)s, lists[0],
+                           at<double>(work, L.eta_prev), cnt, stats);
+    }
+    SweepArgs<float> sa{};
+    sa.n = (int)n;
+    sa.count = (int)s;
+    sa.H = h->H32;
+    sa.ldh = h->ldh;
+    sa.shifts = shifts;
+    sa.list = nullptr;
+    sa.Rtop = h->Rtop;
+    sa.refl = at<float>(work, L.refl32);
+    sa.refl_stride = g32s.stride;
+    sa.Y = at<float>(work, L.y32);
+    sa.y_stride = 2 * m * m;
+    sa.status = st2;
+    {
+        PhaseScope ps(h, PH_SWEEP32, s, st);
+        if (!launch_sweep((int)m, false, sa, st)) return hipErrorInvalidValue;
+    }
+    QstarArgs<float> qa{};
+    qa.n = (int)n;
+    qa.count = (int)s;
+    qa.list = nullptr;
+    qa.refl = sa.refl;
+    qa.refl_stride = g32s.stride;
+    qa.tile_rows = g32s.g.tile_rows;
+    qa.tile_stride = g32s.g.tile_stride;
+    qa.slot = g32s.g.slot;
+    qa.Y = sa.Y;
+    qa.y_stride = 2 * m * m;
+    qa.X = Xw;
+    qa.ldx = ldxw;
+    qa.accumulate = 0;
+    {
+        PhaseScope ps(h, PH_QSTAR, s, st);
+        if (!launch_qstar((int)m, false, qa, st)) return hipErrorInvalidValue;
+    }
+    for (int it = 0;; ++it) {
+        int32_t *in = lists[it & 1], *out = lists[(it + 1) & 1];
+        const int *cin = cnt + (it & 1);
+        int *cout = cnt + ((it + 1) & 1);
+        e = certify(h, s, in, cin, shifts, Xw, ldxw, Res, at<unsigned long long>(work, L.resmax),
+                    at<unsigned long long>(work, L.xmax), eta, nullptr, s, at<double>(work, L.xt), st);
+        if (e != hipSuccess) return e;
+        {
+            PhaseScope ps(h, PH_OTHER, s, st);
+            hipLaunchKernelGGL(mixed_select_kernel, dim3(1), dim3(1024), 0, st, it, max_iter, tol,
+                               (const int32_t *)in, cin, out, cout, fbl, cnt + 2, (const double *)eta,
+                               at<double>(work, L.eta_prev), status, stats);
+        }
+        if (it >= max_iter) break;
+        // correction: (H - sigma I) D = Res in FP32 (scaled), X += scale D
+        {
+            PhaseScope ps(h, PH_OTHER, s, st);
+            hipLaunchKernelGGL(scale_residual_kernel, dim3((unsigned)s, std::max<unsigned>(1, cdiv(n * m, 256 * 16))),
+                               dim3(256), 0, st, (int)n, (int)m, (const int *)cout, (const int32_t *)out,
+                               (const double *)Res, (const unsigned long long *)at<unsigned long long>(work, L.resmax),
+                               at<double>(work, L.scale), at<float>(work, L.e32));
+        }
+        SweepArgs<float> da{};
+        da.n = (int)n;
+        da.count = (int)s;
+        da.H = h->H32;
+        da.ldh = h->ldh;
+        da.shifts = shifts;
+        da.list = out;
+        da.Rtop = h->Rtop;
+        da.E = at<float>(work, L.e32);
+        da.e_stride = 2 * n * m;
+        da.refl = at<float>(work, L.refl32);
+        da.refl_stride = g32d.stride;
+        da.Y = at<float>(work, L.yd32);
+        da.y_stride = 2 * n * m;
+        da.status = st2;
+        da.dcount = cout;
+        {
+            PhaseScope ps(h, PH_SWEEP32D, s, st);
+            if (!launch_sweep((int)m, true, da, st)) return hipErrorInvalidValue;
+        }
+        QstarArgs<float> dq{};
+        dq.n = (int)n;
+        dq.count = (int)s;
+        dq.list = out;
+        dq.refl = da.refl;
+        dq.refl_stride = g32d.stride;
+        dq.tile_rows = g32d.g.tile_rows;
+        dq.tile_stride = g32d.g.tile_stride;
+        dq.slot = g32d.g.slot;
+        dq.Y = da.Y;
+        dq.y_stride = 2 * n * m;
+        dq.X = Xw;
+        dq.ldx = ldxw;
+        dq.accumulate = 1;
+        dq.scale = at<double>(work, L.scale);
+        dq.dcount = cout;
+        {
+            PhaseScope ps(h, PH_QSTAR, s, st);
+            if (!launch_qstar((int)m, true, dq, st)) return hipErrorInvalidValue;
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // FP64 sweep for the shifts the mixed form could not certify (the
+    // refinement buffers are dead now; the blocked sweep reuses them)
+    e = solve_fp64(h, s, fbl, cnt + 2, shifts, work, L, Xw, ldxw, st2, st);
+    if (e != hipSuccess) return e;
+    e = certify(h, s, fbl, cnt + 2, shifts, Xw, ldxw, nullptr, at<unsigned long long>(work, L.resmax),
+                at<unsigned long long>(work, L.xmax), eta, st2, s, at<double>(work, L.xt), st);
+    if (e != hipSuccess) return e;
+    {
+        PhaseScope ps(h, PH_OTHER, s, st);
+        hipLaunchKernelGGL(mixed_final_kernel, dim3(cdiv(s, 256)), dim3(256), 0, st, (const int *)(cnt + 2),
+                           (const int32_t *)fbl, (const int32_t *)st2, (const double *)eta, tol, status);
+    }
     return hipGetLastError();
 }
 
@@ -626,6 +893,8 @@ const char *shs_strerror(int code)
     case SHS_ERR_BUSY: return "busy";
     case SHS_ERR_NOTFOUND: return "unknown id";
     case SHS_ERR_TIMEOUT: return "timed out";
+    case SHS_ERR_CANCELLED: return "cancelled";
+    case SHS_ERR_STATE: return "request already finished or not finished";
     default: return "unknown error";
     }
 }
@@ -678,6 +947,7 @@ int shs_reduce(int64_t n, int64_t m, int64_t p, const double *A, int64_t lda, co
     ALLOC(h->sgn, n);
     ALLOC(h->offrow, n);
     ALLOC(h->diag, n);
+    ALLOC(h->dstats, 4);
 #undef ALLOC
     e = hipMalloc((void **)&part, sizeof(double) * (size_t)std::max<int64_t>(n, 1) * cdiv(n, kRightChunk));
     if (e != hipSuccess) goto fail;
@@ -759,6 +1029,43 @@ fail:
     return e == hipErrorOutOfMemory ? SHS_ERR_NOMEM : SHS_ERR_HIP;
 }
 
+int shs_reduce_check_plan(int64_t n, int64_t m, int64_t p, int64_t *launches, char *msg, int64_t msg_len)
+{
+    if (n < 2) return -1;
+    if (m < 1 || m >= n || m > SHS_MAX_M) return -2;
+    if (p < 0) return -3;
+    if (n > (int64_t)INT32_MAX / 2) return SHS_ERR_UNSUPPORTED;
+    // the allocations shs_reduce makes, at distinct addresses that are never
+    // dereferenced (1 TiB apart, 256-byte aligned like hipMalloc's)
+    shs_handle h;
+    h.n = n;
+    h.m = m;
+    h.p = p;
+    h.ldh = (n + 15) / 16 * 16;
+    h.ldct = std::max<int64_t>(1, p);
+    h.nrefl = m + std::max<int64_t>(0, n - m - 1);
+    LaunchCheck chk;
+    uintptr_t base = (uintptr_t)1 << 40;
+    auto region = [&](size_t elems, const char *name) {
+        double *p0 = reinterpret_cast<double *>(base);
+        chk.add(p0, std::max<size_t>(elems, 1), name);
+        base += (uintptr_t)1 << 40;
+        return p0;
+    };
+    h.H = region((size_t)(h.ldh * n), "H");
+    h.Ct = region((size_t)(h.ldct * n), "Ct");
+    h.V = region((size_t)(n * h.nrefl), "V");
+    h.tauv = region((size_t)h.nrefl, "tau");
+    double *bwork = region(reduce_blocked_work(n, m, p) / sizeof(double), "work");
+    hipError_t e = reduce_blocked(&h, bwork, nullptr, &chk);
+    h.H = nullptr;   // the handle owns nothing here
+    h.Ct = h.V = h.tauv = nullptr;
+    if (launches) *launches = chk.launches;
+    if (msg && msg_len > 0) snprintf(msg, (size_t)msg_len, "%s", chk.violations ? chk.first : "");
+    if (e != hipSuccess) return SHS_ERR_HIP;
+    return (int)std::min<int64_t>(chk.violations, INT32_MAX);
+}
+
 int shs_solve_workspace(const shs_handle *h, int64_t s, int mode, int outputs, size_t *bytes)
 {
     if (!h) return -1;
@@ -794,8 +1101,7 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outp
     if (!layout(h, s, mode, outputs, &L)) return SHS_ERR_UNSUPPORTED;
     if (h->timing) {   // timing state is only touched when enabled (see shs_set_timing)
         h->marks.clear();
-        h->refine_iterations = 0;
-        h->fallback_shifts = 0;
+        h->last_mixed = mode == SHS_MODE_FP32_REFINE;
         h->tile_flops = h->update_flops = 0.0;
     }
     bool owned = false;
@@ -811,151 +1117,12 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outp
     hipError_t e = hipSuccess;
 
     if (mode == SHS_MODE_FP64) {
-        e = solve_fp64(h, s, nullptr, shifts, work, L, Xw, ldxw, status, st);
+        e = solve_fp64(h, s, nullptr, nullptr, shifts, work, L, Xw, ldxw, status, st);
         if (e == hipSuccess && (outputs & SHS_OUT_ETA))
-            e = certify(h, s, nullptr, shifts, Xw, ldxw, nullptr, at<unsigned long long>(work, L.resmax),
+            e = certify(h, s, nullptr, nullptr, shifts, Xw, ldxw, nullptr, at<unsigned long long>(work, L.resmax),
                         at<unsigned long long>(work, L.xmax), eta, status, s, at<double>(work, L.xt), st);
     } else {
-        // ---- complex FP32 sweep, then FP64 iterative refinement -------------
-        Geo g32s, g32d;
-        geo(true, n, m, false, &g32s);
-        geo(true, n, m, true, &g32d);
-        int32_t *dlist = at<int32_t>(work, L.list);
-        int32_t *st2 = at<int32_t>(work, L.status2);
-        SweepArgs<float> sa{};
-        sa.n = (int)n;
-        sa.count = (int)s;
-        sa.H = h->H32;
-        sa.ldh = h->ldh;
-        sa.shifts = shifts;
-        sa.list = nullptr;
-        sa.Rtop = h->Rtop;
-        sa.refl = at<float>(work, L.refl32);
-        sa.refl_stride = g32s.stride;
-        sa.Y = at<float>(work, L.y32);
-        sa.y_stride = 2 * m * m;
-        sa.status = st2;
-        {
-            PhaseScope ps(h, PH_SWEEP32, s, st);
-            if (!launch_sweep((int)m, false, sa, st)) e = hipErrorInvalidValue;
-        }
-        QstarArgs<float> qa{};
-        qa.n = (int)n;
-        qa.count = (int)s;
-        qa.list = nullptr;
-        qa.refl = sa.refl;
-        qa.refl_stride = g32s.stride;
-        qa.tile_rows = g32s.g.tile_rows;
-        qa.tile_stride = g32s.g.tile_stride;
-        qa.slot = g32s.g.slot;
-        qa.Y = sa.Y;
-        qa.y_stride = 2 * m * m;
-        qa.X = Xw;
-        qa.ldx = ldxw;
-        qa.accumulate = 0;
-        if (e == hipSuccess) {
-            PhaseScope ps(h, PH_QSTAR, s, st);
-            if (!launch_qstar((int)m, false, qa, st)) e = hipErrorInvalidValue;
-        }
-
-        std::vector<int32_t> active(s), next, fallback;
-        for (int64_t j = 0; j < s; ++j) active[j] = (int32_t)j;
-        std::vector<double> heta(s), hprev(s, INFINITY);
-        double *Res = at<double>(work, L.res);
-        for (int it = 0; e == hipSuccess; ++it) {
-            const int64_t na = (int64_t)active.size();
-            if (na == 0) break;
-            e = hipMemcpyAsync(dlist, active.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, st);
-            if (e != hipSuccess) break;
-            e = certify(h, na, dlist, shifts, Xw, ldxw, Res, at<unsigned long long>(work, L.resmax),
-                        at<unsigned long long>(work, L.xmax), eta, nullptr, s, at<double>(work, L.xt), st);
-            if (e != hipSuccess) break;
-            e = hipMemcpyAsync(heta.data(), eta, sizeof(double) * s, hipMemcpyDeviceToHost, st);
-            if (e != hipSuccess) break;
-            e = hipStreamSynchronize(st);
-            if (e != hipSuccess) break;
-            next.clear();
-            for (int32_t j : active) {
-                const double v = heta[j];
-                if (v <= tol) continue;                           // converged
-                if (!(v == v) || it >= max_iter || !(v <= 0.5 * hprev[j])) {
-                    fallback.push_back(j);                        // stagnated or out of iterations
-                    continue;
-                }
-                hprev[j] = v;
-                next.push_back(j);
-            }
-            active.swap(next);
-            if (active.empty()) break;
-            // correction: (H - sigma I) D = Res in FP32 (scaled), X += scale D
-            const int64_t nc = (int64_t)active.size();
-            e = hipMemcpyAsync(dlist, active.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, st);
-            if (e != hipSuccess) break;
-            if (h->timing) h->refine_iterations++;
-            {
-                PhaseScope ps(h, PH_OTHER, nc, st);
-                hipLaunchKernelGGL(scale_residual_kernel, dim3(std::max<unsigned>(1, cdiv(n * m, 256 * 16)), (unsigned)nc),
-                                   dim3(256), 0, st, (int)n, (int)m, (int)nc, (const int32_t *)dlist,
-                                   (const double *)Res,
-                                   (const unsigned long long *)at<unsigned long long>(work, L.resmax),
-                                   at<double>(work, L.scale), at<float>(work, L.e32));
-            }
-            SweepArgs<float> da{};
-            da.n = (int)n;
-            da.count = (int)nc;
-            da.H = h->H32;
-            da.ldh = h->ldh;
-            da.shifts = shifts;
-            da.list = dlist;
-            da.Rtop = h->Rtop;
-            da.E = at<float>(work, L.e32);
-            da.e_stride = 2 * n * m;
-            da.refl = at<float>(work, L.refl32);
-            da.refl_stride = g32d.stride;
-            da.Y = at<float>(work, L.yd32);
-            da.y_stride = 2 * n * m;
-            da.status = st2;
-            {
-                PhaseScope ps(h, PH_SWEEP32D, nc, st);
-                if (!launch_sweep((int)m, true, da, st)) { e = hipErrorInvalidValue; break; }
-            }
-            QstarArgs<float> dq{};
-            dq.n = (int)n;
-            dq.count = (int)nc;
-            dq.list = dlist;
-            dq.refl = da.refl;
-            dq.refl_stride = g32d.stride;
-            dq.tile_rows = g32d.g.tile_rows;
-            dq.tile_stride = g32d.g.tile_stride;
-            dq.slot = g32d.g.slot;
-            dq.Y = da.Y;
-            dq.y_stride = 2 * n * m;
-            dq.X = Xw;
-            dq.ldx = ldxw;
-            dq.accumulate = 1;
-            dq.scale = at<double>(work, L.scale);
-            {
-                PhaseScope ps(h, PH_QSTAR, nc, st);
-                if (!launch_qstar((int)m, true, dq, st)) { e = hipErrorInvalidValue; break; }
-            }
-            e = hipGetLastError();
-        }
-        // converged shifts: status 0
-        if (e == hipSuccess) e = hipMemsetAsync(status, 0, sizeof(int32_t) * s, st);
-        if (e == hipSuccess && !fallback.empty()) {
-            // FP64 sweep for the shifts the mixed form could not certify
-            const int64_t nf = (int64_t)fallback.size();
-            if (h->timing) h->fallback_shifts = nf;
-            e = hipMemcpyAsync(dlist, fallback.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, st);
-            if (e == hipSuccess) e = solve_fp64(h, nf, dlist, shifts, work, L, Xw, ldxw, st2, st);
-            if (e == hipSuccess)
-                e = certify(h, nf, dlist, shifts, Xw, ldxw, nullptr, at<unsigned long long>(work, L.resmax),
-                            at<unsigned long long>(work, L.xmax), eta, st2, s, at<double>(work, L.xt), st);
-            if (e == hipSuccess)
-                hipLaunchKernelGGL(fill_status_kernel, dim3(cdiv(nf, 256)), dim3(256), 0, st, (int)nf,
-                                   (const int32_t *)dlist, (const int32_t *)st2, status, SHS_STATUS_FALLBACK);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-        }
+        e = solve_mixed(h, s, shifts, tol, max_iter, work, L, Xw, ldxw, eta, status, st);
     }
     if (e == hipSuccess && (outputs & SHS_OUT_G) && h->p > 0) {
         PhaseScope ps(h, PH_OTHER, s, st);
@@ -1055,10 +1222,15 @@ int shs_last_timings(const shs_handle *h, shs_timings_t *out)
         *calls[mk.phase] += 1;
         if (mk.phase == PH_SWEEP) out->sweep_shifts += mk.shifts;
         if (mk.phase == PH_SWEEP32) out->sweep32_shifts += mk.shifts;
-        if (mk.phase == PH_SWEEP32D) out->sweep32_dense_shifts += mk.shifts;
     }
-    out->refine_iterations = h->refine_iterations;
-    out->fallback_shifts = h->fallback_shifts;
+    if (h->last_mixed) {
+        // the mixed mode counts its rounds and shifts on the device
+        long long st[3] = {0, 0, 0};
+        RETURN_IF_HIP(hipMemcpy(st, h->dstats, sizeof(st), hipMemcpyDeviceToHost));
+        out->refine_iterations = st[0];
+        out->fallback_shifts = st[1];
+        out->sweep32_dense_shifts = st[2];
+    }
     out->sweep_tile_flops = h->tile_flops;
     out->sweep_update_flops = h->update_flops;
     return 0;

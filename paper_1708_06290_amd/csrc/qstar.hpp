@@ -35,6 +35,7 @@ struct QstarArgs {
     int64_t ldx;
     int accumulate;              // 0: X = D, 1: X += scale[sid] * D
     const double *scale;         // per shift id, or nullptr (= 1)
+    const int *dcount;           // if set, the number of work items is read here (count is an upper bound)
 };
 
 // One lane's share of the Q* pass: column c of one shift.  rf is the
@@ -144,7 +145,8 @@ __global__ __launch_bounds__(64) void qstar_kernel(QstarArgs<T> a)
     const int lane = threadIdx.x;
     const int sw = lane / M, c = lane % M;
     const int item = blockIdx.x * SPW + sw;
-    const bool active = (sw < SPW) && (item < a.count);
+    const int count = a.dcount ? *a.dcount : a.count;
+    const bool active = (sw < SPW) && (item < count);
     const int sid = active ? (a.list ? a.list[item] : item) : 0;
     const T *rf = a.refl + (int64_t)sid * a.refl_stride;
     const T *Y = a.Y + (int64_t)sid * a.y_stride;
@@ -244,9 +246,11 @@ __global__ __launch_bounds__(64) void qstar_wave_kernel(QstarArgs<T> a, int spw)
     const int lq = lane / gl, ll = lane % gl;    // loader: shift, lane within
     const int q = lane / M, c = lane % M;        // compute: shift, column
     const int item = blockIdx.x * spw + q;
-    const bool active = q < spw && item < a.count;
+    const int count = a.dcount ? *a.dcount : a.count;
+    if (blockIdx.x * spw >= count) return;   // uniform: no shift of this wave is listed
+    const bool active = q < spw && item < count;
     const int litem = blockIdx.x * spw + lq;
-    const bool lact = litem < a.count;
+    const bool lact = litem < count;
     const int sid = active ? (a.list ? a.list[item] : item) : 0;
     const int lsid = lact ? (a.list ? a.list[litem] : litem) : 0;
     const T *rf = a.refl + (int64_t)lsid * a.refl_stride;

@@ -31,6 +31,7 @@ struct ResidualArgs {
     int64_t ldr;
     unsigned long long *resmax; // per column (s m), max |Res| (bits of a non-negative double)
     unsigned long long *xmax;   // per column, max |X|
+    const int *dcount;          // if set, the number of listed shifts is read here (count is an upper bound)
 };
 
 typedef double shs_dbl4 __attribute__((ext_vector_type(4)));
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(256) void residual_pack_kernel(ResidualArgs a)
     __shared__ double tr[TK][TW + 1], ti[TK][TW + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int k0 = blockIdx.x * TK, w0 = blockIdx.y * TW;
-    const int ncols = a.count * a.m, m = a.m;
+    const int ncols = (a.dcount ? *a.dcount : a.count) * a.m, m = a.m;
     double xr[PER], xi[PER];
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
@@ -113,10 +114,11 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
     auto Xs = reinterpret_cast<double (*)[BK][BN]>(res_smem + 2 * BK * BM);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int ncols = a.count * a.m;
+    const int ncols = (a.dcount ? *a.dcount : a.count) * a.m;
     const int n = a.n, m = a.m;
     const int i0 = blockIdx.x * BM;
     const int w0 = blockIdx.y * (BN / 2);   // first complex column of the tile
+    if (w0 >= ncols) return;                // uniform: the tile holds no listed column
     const int q = lane % 16;
     const bool re_lane = q < 8;
 
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
 }
 
 // eta per listed shift; updates status (NaN -> NONFINITE).
-__global__ __launch_bounds__(256) void eta_kernel(int n, int m, int count, const int32_t *list,
+__global__ __launch_bounds__(256) void eta_kernel(int n, int m, int count, const int *dcount, const int32_t *list,
                                                   const double *shifts, const double *offrow,
                                                   const double *diag, const double *rcolmax,
                                                   const unsigned long long *resmax,
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(256) void eta_kernel(int n, int m, int count, const
                                                   double *eta, int32_t *status)
 {
     const int item = blockIdx.x;
-    if (item >= count) return;
+    if (item >= (dcount ? *dcount : count)) return;
     const int sid = list ? list[item] : item;
     const double sr = shifts[2 * sid], si = shifts[2 * sid + 1];
     double nh = 0.0;

@@ -2,13 +2,19 @@
 // continuous batching of shift requests (shs_server_* in shiftsolve.h).
 //
 // Worker threads each own a HIP stream.  A free worker takes the oldest
-// waiting request; if it is FP64 it also takes every other waiting FP64
-// request that still fits in the memory budget (any system, any n and m)
-// and runs all their shifts in one launch of the work-item kernel, then
-// forms G and the backward error per request.  A mixed-precision request is
-// run alone with shs_solve.  Requests submitted meanwhile wait in the queue
-// and are admitted by the next free worker, so work from different requests
-// overlaps on the device through the workers' streams.
+// waiting request.  A request on the work-item route (FP64, one shift small
+// enough for one wavefront) takes every other waiting work-item request that
+// still fits in the memory budget (any system, any n and m) and runs all
+// their shifts in one launch of the work-item kernel, then forms G and the
+// backward error per request.  A request on the solve route (mixed
+// precision, or FP64 on a system whose shifts need the blocked sweep) takes
+// the other waiting requests of the same system, mode and outputs that fit,
+// and runs their shifts as one shs_solve.  Requests submitted meanwhile wait
+// in the queue and are admitted by the next free worker, so work from
+// different requests overlaps on the device through the workers' streams.
+// Every kernel of the library computes each shift independently of the
+// others in its launch, so a request's results are bitwise the same alone
+// and in any batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,9 +49,11 @@ struct Request {
     int64_t ldx = 0, ldg = 0;
     int32_t *status = nullptr;
     size_t footprint = 0;
-    bool alone = false;           // runs as its own shs_solve (mixed mode, or blocked FP64)
-    Clock::time_point t_submit, t_done;
-    int state = 0;                // 0 queued, 1 running, 2 done, 3 failed
+    bool alone = false;           // solve route: shs_solve (mixed mode, or blocked FP64)
+    Clock::time_point t_arrival, t_done;
+    hipEvent_t after = nullptr;   // the caller's stream at submit: the request's work waits for it
+    int state = 0;                // SHS_REQ_* (queued, running, done, failed, cancelled)
+    bool cancel = false;          // cancelled while running: marked so on completion
     int error = 0;
 };
 
@@ -80,19 +88,36 @@ struct shs_server {
     std::unordered_map<int64_t, std::shared_ptr<Request>> reqs;
     int64_t next_id = 1;
     size_t in_use = 0, peak = 0;
-    bool stop = false;
+    bool stop = false, paused = false;
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
     // statistics
-    int64_t submitted = 0, completed = 0, failed = 0, running = 0, solves = 0, batches = 0, max_sys = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, cancelled = 0, running = 0, solves = 0, batches = 0,
+            max_sys = 0, max_reqs = 0;
     std::vector<double> lat_ms;
     bool any = false;
     Clock::time_point t_first, t_last;
 
     void worker(int wid);
     int run_fp64_batch(std::vector<std::shared_ptr<Request>> &batch, hipStream_t st);
-    int run_alone(Request &r, hipStream_t st);
+    int run_solve_batch(std::vector<std::shared_ptr<Request>> &batch, hipStream_t st);
+    size_t solve_batch_bytes(const shs_handle *h, int64_t s, int mode, int outputs) const;
 };
+
+namespace {
+
+// The stream waits for the callers' streams of every request in the batch.
+hipError_t wait_callers(const std::vector<std::shared_ptr<Request>> &batch, hipStream_t st)
+{
+    for (auto &r : batch)
+        if (r->after) {
+            hipError_t e = hipStreamWaitEvent(st, r->after, 0);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
+}  // namespace
 
 int shs_server::run_fp64_batch(std::vector<std::shared_ptr<Request>> &batch, hipStream_t st)
 {
@@ -120,8 +145,10 @@ int shs_server::run_fp64_batch(std::vector<std::shared_ptr<Request>> &batch, hip
     total += al256(sizeof(ServeItem) * (size_t)nitems);
     const size_t counter_off = total;
     total += 256;
+    hipError_t e = wait_callers(batch, st);
+    if (e != hipSuccess) return SHS_ERR_HIP;
     char *work = nullptr;
-    hipError_t e = hipMallocAsync((void **)&work, total, st);
+    e = hipMallocAsync((void **)&work, total, st);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? SHS_ERR_NOMEM : SHS_ERR_HIP;
 
     std::vector<ServeItem> items;
@@ -170,7 +197,7 @@ int shs_server::run_fp64_batch(std::vector<std::shared_ptr<Request>> &batch, hip
         const int64_t ldx = (r.outputs & SHS_OUT_X) ? r.ldx : h->n;
         if ((r.outputs & SHS_OUT_G) && h->p > 0) e = g_eval(h, r.s, X, ldx, r.G, r.ldg, st);
         if (e == hipSuccess && (r.outputs & SHS_OUT_ETA))
-            e = certify(h, r.s, nullptr, (const double *)(work + offs[b].shifts), X, ldx, nullptr,
+            e = certify(h, r.s, nullptr, nullptr, (const double *)(work + offs[b].shifts), X, ldx, nullptr,
                         (unsigned long long *)(work + offs[b].resmax), (unsigned long long *)(work + offs[b].xmax),
                         r.eta, r.status, r.s, (double *)(work + offs[b].xt), st);
     }
@@ -180,18 +207,84 @@ int shs_server::run_fp64_batch(std::vector<std::shared_ptr<Request>> &batch, hip
     return e == hipSuccess ? 0 : (e == hipErrorOutOfMemory ? SHS_ERR_NOMEM : SHS_ERR_HIP);
 }
 
-int shs_server::run_alone(Request &r, hipStream_t st)
+// Device bytes of one shs_solve over s shifts of h on the solve route: the
+// solve's workspace, the shifts and the batch's own X, G, eta and status
+// (the requests' outputs are filled from them).
+size_t shs_server::solve_batch_bytes(const shs_handle *h, int64_t s, int mode, int outputs) const
 {
-    shs_handle *h = systems[r.sys];
-    double *dsh = nullptr;
-    hipError_t e = hipMallocAsync((void **)&dsh, sizeof(double) * 2 * r.s, st);
-    if (e != hipSuccess) return SHS_ERR_NOMEM;
-    e = hipMemcpyAsync(dsh, r.shifts.data(), sizeof(double) * 2 * r.s, hipMemcpyHostToDevice, st);
+    size_t ws = 0;
+    if (shs_solve_workspace(h, s, mode, outputs, &ws) != 0) return (size_t)-1;
+    const size_t x = (outputs & SHS_OUT_X) ? al256(sizeof(double) * 2 * (size_t)(h->n * h->m * s)) : 0;
+    const size_t g = (outputs & SHS_OUT_G) && h->p > 0 ? al256(sizeof(double) * 2 * (size_t)(h->p * h->m * s)) : 0;
+    return al256(ws) + x + g + 3 * al256(sizeof(double) * 2 * (size_t)s);
+}
+
+int shs_server::run_solve_batch(std::vector<std::shared_ptr<Request>> &batch, hipStream_t st)
+{
+    const Request &r0 = *batch[0];
+    shs_handle *h = systems[r0.sys];
+    const int64_t n = h->n, m = h->m, p = h->p;
+    int64_t S = 0;
+    for (auto &r : batch) S += r->s;
+    const bool one = batch.size() == 1;
+    size_t ws = 0;
+    if (shs_solve_workspace(h, S, r0.mode, r0.outputs, &ws) != 0) return SHS_ERR_UNSUPPORTED;
+    // a single request writes straight into its own outputs
+    const bool wx = (r0.outputs & SHS_OUT_X) && !one, wg = (r0.outputs & SHS_OUT_G) && p > 0 && !one;
+    size_t total = 0;
+    auto take = [&](size_t bytes) { size_t o = total; total += al256(bytes); return o; };
+    const size_t o_ws = take(ws);
+    const size_t o_sh = take(sizeof(double) * 2 * S);
+    const size_t o_x = wx ? take(sizeof(double) * 2 * n * m * S) : 0;
+    const size_t o_g = wg ? take(sizeof(double) * 2 * p * m * S) : 0;
+    const size_t o_eta = one ? 0 : take(sizeof(double) * S);
+    const size_t o_st = one ? 0 : take(sizeof(int32_t) * S);
+    hipError_t e = wait_callers(batch, st);
+    if (e != hipSuccess) return SHS_ERR_HIP;
+    char *work = nullptr;
+    e = hipMallocAsync((void **)&work, total, st);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? SHS_ERR_NOMEM : SHS_ERR_HIP;
+    int64_t off = 0;
+    for (auto &r : batch) {
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(work + o_sh + sizeof(double) * 2 * off, r->shifts.data(), sizeof(double) * 2 * r->s,
+                               hipMemcpyHostToDevice, st);
+        off += r->s;
+    }
     int rc = e == hipSuccess ? 0 : SHS_ERR_HIP;
+    double *X = one ? r0.X : (double *)(work + o_x);
+    const int64_t ldx = one ? r0.ldx : n;
+    double *G = one ? r0.G : (double *)(work + o_g);
+    const int64_t ldg = one ? r0.ldg : std::max<int64_t>(1, p);
+    double *eta = one ? r0.eta : (double *)(work + o_eta);
+    int32_t *status = one ? r0.status : (int32_t *)(work + o_st);
+    if (!one) {
+        // a batch certifies every shift (mixed mode needs eta in any case)
+        if (!(r0.outputs & SHS_OUT_X)) X = nullptr;
+        if (!((r0.outputs & SHS_OUT_G) && p > 0)) G = nullptr;
+    }
     if (rc == 0)
-        rc = shs_solve(h, r.s, dsh, r.mode, r.outputs, 1e-13, 5, nullptr, 0, r.X, r.ldx, r.G, r.ldg, r.eta, r.status,
-                       st);
-    hipFreeAsync(dsh, st);
+        rc = shs_solve(h, S, (const double *)(work + o_sh), r0.mode, r0.outputs | (one ? 0 : SHS_OUT_ETA), 1e-13, 5,
+                       work + o_ws, ws, X, ldx, G, ldg, eta, status, st);
+    // scatter the batch's outputs to the requests
+    off = 0;
+    for (auto &r : batch) {
+        if (rc != 0 || one) break;
+        const int64_t c0 = off * m, nc = r->s * m;
+        if (r->outputs & SHS_OUT_X)
+            e = hipMemcpy2DAsync(r->X, sizeof(double) * 2 * r->ldx, X + 2 * c0 * n, sizeof(double) * 2 * n,
+                                 sizeof(double) * 2 * n, nc, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && (r->outputs & SHS_OUT_G) && p > 0)
+            e = hipMemcpy2DAsync(r->G, sizeof(double) * 2 * r->ldg, G + 2 * c0 * ldg, sizeof(double) * 2 * ldg,
+                                 sizeof(double) * 2 * p, nc, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && r->eta)
+            e = hipMemcpyAsync(r->eta, eta + off, sizeof(double) * r->s, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r->status, status + off, sizeof(int32_t) * r->s, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) rc = SHS_ERR_HIP;
+        off += r->s;
+    }
+    hipFreeAsync(work, st);
     e = hipStreamSynchronize(st);
     if (rc == 0 && e != hipSuccess) rc = SHS_ERR_HIP;
     return rc;
@@ -208,22 +301,37 @@ void shs_server::worker(int wid)
             std::unique_lock<std::mutex> lk(mu);
             for (;;) {
                 if (stop && pending.empty()) return;
-                if (!pending.empty()) {
+                if (!pending.empty() && !paused) {
                     auto head = pending.front();
-                    if (in_use + head->footprint <= budget) {
+                    const shs_handle *hh = systems[head->sys];
+                    const size_t head_fp =
+                        head->alone ? solve_batch_bytes(hh, head->s, head->mode, head->outputs) : head->footprint;
+                    if (in_use + head_fp <= budget) {
                         pending.pop_front();
                         batch.push_back(head);
-                        fp = head->footprint;
-                        if (!head->alone) {
-                            // every other waiting work-item request that fits joins the launch
-                            for (auto it = pending.begin(); it != pending.end() && (int)batch.size() < max_batch;) {
-                                if (!(*it)->alone && in_use + fp + (*it)->footprint <= budget) {
-                                    fp += (*it)->footprint;
-                                    batch.push_back(*it);
-                                    it = pending.erase(it);
-                                } else {
-                                    ++it;
-                                }
+                        fp = head_fp;
+                        int64_t S = head->s;
+                        for (auto it = pending.begin(); it != pending.end() && (int)batch.size() < max_batch;) {
+                            const Request &r = **it;
+                            bool join = false;
+                            size_t nfp = 0;
+                            if (!head->alone && !r.alone) {
+                                // work-item route: any system
+                                nfp = fp + r.footprint;
+                                join = true;
+                            } else if (head->alone && r.alone && r.sys == head->sys && r.mode == head->mode &&
+                                       r.outputs == head->outputs) {
+                                // solve route: the same system, mode and outputs
+                                nfp = solve_batch_bytes(hh, S + r.s, head->mode, head->outputs);
+                                join = true;
+                            }
+                            if (join && in_use + nfp <= budget) {
+                                fp = nfp;
+                                S += r.s;
+                                batch.push_back(*it);
+                                it = pending.erase(it);
+                            } else {
+                                ++it;
                             }
                         }
                         break;
@@ -234,16 +342,15 @@ void shs_server::worker(int wid)
             in_use += fp;
             peak = std::max(peak, in_use);
             running += (int64_t)batch.size();
-            for (auto &r : batch) r->state = 1;
-            if (!batch[0]->alone) {
-                ++batches;
-                std::vector<int32_t> sy;
-                for (auto &r : batch) sy.push_back(r->sys);
-                std::sort(sy.begin(), sy.end());
-                max_sys = std::max<int64_t>(max_sys, std::unique(sy.begin(), sy.end()) - sy.begin());
-            }
+            for (auto &r : batch) r->state = SHS_REQ_RUNNING;
+            ++batches;
+            std::vector<int32_t> sy;
+            for (auto &r : batch) sy.push_back(r->sys);
+            std::sort(sy.begin(), sy.end());
+            max_sys = std::max<int64_t>(max_sys, std::unique(sy.begin(), sy.end()) - sy.begin());
+            max_reqs = std::max<int64_t>(max_reqs, (int64_t)batch.size());
         }
-        const int rc = batch[0]->alone ? run_alone(*batch[0], st) : run_fp64_batch(batch, st);
+        const int rc = batch[0]->alone ? run_solve_batch(batch, st) : run_fp64_batch(batch, st);
         const auto now = Clock::now();
         {
             std::lock_guard<std::mutex> lk(mu);
@@ -252,12 +359,20 @@ void shs_server::worker(int wid)
             for (auto &r : batch) {
                 r->t_done = now;
                 r->error = rc;
-                r->state = rc == 0 ? 2 : 3;
-                if (rc == 0) {
+                if (r->after) {
+                    hipEventDestroy(r->after);
+                    r->after = nullptr;
+                }
+                if (r->cancel) {
+                    r->state = SHS_REQ_CANCELLED;
+                    ++cancelled;
+                } else if (rc == 0) {
+                    r->state = SHS_REQ_DONE;
                     ++completed;
                     solves += r->s;
-                    lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->t_submit).count());
+                    lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->t_arrival).count());
                 } else {
+                    r->state = SHS_REQ_FAILED;
                     ++failed;
                 }
             }
@@ -269,6 +384,11 @@ void shs_server::worker(int wid)
 }
 
 extern "C" {
+
+double shs_server_clock(void)
+{
+    return std::chrono::duration<double>(Clock::now().time_since_epoch()).count();
+}
 
 int shs_server_create(const shs_server_config *cfg, shs_server **out)
 {
@@ -310,11 +430,12 @@ int shs_server_register(shs_server *srv, shs_handle *h, int32_t *sys_id)
     return 0;
 }
 
-int shs_server_submit(shs_server *srv, int32_t sys_id, int64_t s, const double *shifts_host, int mode, int outputs,
-                      double *X, int64_t ldx, double *G, int64_t ldg, double *eta, int32_t *status, int64_t *req_id)
+int shs_server_submit_ex(shs_server *srv, int32_t sys_id, int64_t s, const double *shifts_host, int mode,
+                         int outputs, double *X, int64_t ldx, double *G, int64_t ldg, double *eta, int32_t *status,
+                         const shs_request_opts *opts, int64_t *req_id)
 {
     if (!srv) return -1;
-    if (!req_id) return -13;
+    if (!req_id) return -14;
     shs_handle *h = nullptr;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
@@ -329,6 +450,7 @@ int shs_server_submit(shs_server *srv, int32_t sys_id, int64_t s, const double *
     if ((outputs & SHS_OUT_G) && h->p > 0 && (!G || ldg < h->p)) return -9;
     if (((outputs & SHS_OUT_ETA) || mode == SHS_MODE_FP32_REFINE) && !eta) return -11;
     if (!status) return -12;
+    if (opts && opts->abi_version != SHS_ABI_VERSION) return -13;
     auto r = std::make_shared<Request>();
     r->sys = sys_id;
     r->s = s;
@@ -345,30 +467,43 @@ int shs_server_submit(shs_server *srv, int32_t sys_id, int64_t s, const double *
     // work-item kernel: such FP64 requests take the blocked solve
     const double shift_flops = (8.0 * h->m + 2.0) * (double)h->n * (double)h->n;
     r->alone = mode != SHS_MODE_FP64 || (srv->blocked_flops >= 0.0 && shift_flops > srv->blocked_flops);
-    if (!r->alone) {
-        r->footprint = fp64_item_bytes(h, s);
-    } else {
-        size_t b = 0;
-        const int rc = shs_solve_workspace(h, s, mode, outputs, &b);
-        if (rc != 0) return rc;
-        r->footprint = b + sizeof(double) * 2 * s;
-    }
+    r->footprint = r->alone ? srv->solve_batch_bytes(h, s, mode, outputs) : fp64_item_bytes(h, s);
     if (r->footprint > srv->budget) return SHS_ERR_NOMEM;
-    r->t_submit = Clock::now();
+    if (opts && opts->order_after) {
+        // the request's work starts after what the caller queued on its stream
+        hipSetDevice(srv->device);
+        if (hipEventCreateWithFlags(&r->after, hipEventDisableTiming) != hipSuccess) return SHS_ERR_HIP;
+        if (hipEventRecord(r->after, (hipStream_t)opts->after_stream) != hipSuccess) {
+            hipEventDestroy(r->after);
+            return SHS_ERR_HIP;
+        }
+    }
+    const auto now = Clock::now();
+    r->t_arrival = now;
+    if (opts && opts->arrival_s > 0.0) {
+        const auto t = Clock::time_point(std::chrono::duration_cast<Clock::duration>(
+            std::chrono::duration<double>(opts->arrival_s)));
+        if (t < now) r->t_arrival = t;
+    }
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         r->id = srv->next_id++;
         srv->reqs[r->id] = r;
         srv->pending.push_back(r);
         ++srv->submitted;
-        if (!srv->any) {
-            srv->any = true;
-            srv->t_first = r->t_submit;
-        }
+        if (!srv->any || r->t_arrival < srv->t_first) srv->t_first = r->t_arrival;
+        srv->any = true;
         *req_id = r->id;
     }
     srv->cv_work.notify_one();
     return 0;
+}
+
+int shs_server_submit(shs_server *srv, int32_t sys_id, int64_t s, const double *shifts_host, int mode, int outputs,
+                      double *X, int64_t ldx, double *G, int64_t ldg, double *eta, int32_t *status, int64_t *req_id)
+{
+    return shs_server_submit_ex(srv, sys_id, s, shifts_host, mode, outputs, X, ldx, G, ldg, eta, status, nullptr,
+                                req_id);
 }
 
 int shs_server_poll(shs_server *srv, int64_t req_id, int *state)
@@ -389,13 +524,56 @@ int shs_server_wait(shs_server *srv, int64_t req_id, double timeout_ms)
     auto it = srv->reqs.find(req_id);
     if (it == srv->reqs.end()) return SHS_ERR_NOTFOUND;
     auto r = it->second;
-    auto done = [&] { return r->state >= 2; };
+    auto done = [&] { return r->state >= SHS_REQ_DONE; };
     if (timeout_ms < 0) {
         srv->cv_done.wait(lk, done);
     } else if (!srv->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), done)) {
         return SHS_ERR_TIMEOUT;
     }
-    return r->state == 2 ? 0 : r->error;
+    if (r->state == SHS_REQ_DONE) return 0;
+    return r->state == SHS_REQ_CANCELLED ? SHS_ERR_CANCELLED : r->error;
+}
+
+int shs_server_cancel(shs_server *srv, int64_t req_id)
+{
+    if (!srv) return -1;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        auto it = srv->reqs.find(req_id);
+        if (it == srv->reqs.end()) return SHS_ERR_NOTFOUND;
+        auto r = it->second;
+        if (r->state == SHS_REQ_QUEUED) {
+            for (auto q = srv->pending.begin(); q != srv->pending.end(); ++q)
+                if (q->get() == r.get()) {
+                    srv->pending.erase(q);
+                    break;
+                }
+            if (r->after) {
+                hipEventDestroy(r->after);
+                r->after = nullptr;
+            }
+            r->state = SHS_REQ_CANCELLED;
+            ++srv->cancelled;
+        } else if (r->state == SHS_REQ_RUNNING) {
+            r->cancel = true;   // it completes; it is then marked cancelled
+        } else {
+            return SHS_ERR_STATE;
+        }
+    }
+    srv->cv_done.notify_all();
+    srv->cv_work.notify_all();
+    return 0;
+}
+
+int shs_server_pause(shs_server *srv, int paused)
+{
+    if (!srv) return -1;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->paused = paused != 0;
+    }
+    srv->cv_work.notify_all();
+    return 0;
 }
 
 int shs_server_latency(shs_server *srv, int64_t req_id, double *ms)
@@ -405,8 +583,8 @@ int shs_server_latency(shs_server *srv, int64_t req_id, double *ms)
     std::lock_guard<std::mutex> lk(srv->mu);
     auto it = srv->reqs.find(req_id);
     if (it == srv->reqs.end()) return SHS_ERR_NOTFOUND;
-    if (it->second->state < 2) return SHS_ERR_BUSY;
-    *ms = std::chrono::duration<double, std::milli>(it->second->t_done - it->second->t_submit).count();
+    if (it->second->state != SHS_REQ_DONE) return SHS_ERR_STATE;
+    *ms = std::chrono::duration<double, std::milli>(it->second->t_done - it->second->t_arrival).count();
     return 0;
 }
 
@@ -419,11 +597,13 @@ int shs_server_stats(shs_server *srv, shs_server_stats_t *out)
     out->submitted = srv->submitted;
     out->completed = srv->completed;
     out->failed = srv->failed;
+    out->cancelled = srv->cancelled;
     out->queued = (int64_t)srv->pending.size();
     out->running = srv->running;
     out->solves = srv->solves;
     out->batches = srv->batches;
     out->max_batch_systems = srv->max_sys;
+    out->max_batch_requests = srv->max_reqs;
     out->peak_bytes = (int64_t)srv->peak;
     if (!srv->lat_ms.empty()) {
         std::vector<double> v = srv->lat_ms;
@@ -451,10 +631,13 @@ void shs_server_destroy(shs_server *srv)
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->stop = true;
+        srv->paused = false;
     }
     srv->cv_work.notify_all();
     for (auto &t : srv->workers) t.join();
     for (hipStream_t st : srv->streams) hipStreamDestroy(st);
+    for (auto &kv : srv->reqs)
+        if (kv.second->after) hipEventDestroy(kv.second->after);
     delete srv;
 }
 

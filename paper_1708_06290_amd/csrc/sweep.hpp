@@ -92,6 +92,7 @@ struct SweepArgs {
     T *Y;                      // structured: m x m complex (ld m); dense: n x m (ld n)
     int64_t y_stride;
     int32_t *status;           // per shift id
+    const int *dcount;         // if set, the number of work items is read here (count is then an upper bound)
 };
 
 // Compile-time shape of one kernel instance.
@@ -659,7 +660,7 @@ __global__ __launch_bounds__(64, 2) void sweep_kernel(SweepArgs<T> a)
 {
     __shared__ T lds[sweep_lds_elems<T, M, DENSE>()];
     const int item = blockIdx.x;
-    if (item >= a.count) return;
+    if (item >= (a.dcount ? *a.dcount : a.count)) return;
     const int sid = a.list ? a.list[item] : item;
     SweepItem<T> it;
     it.n = a.n;

@@ -22,7 +22,9 @@ MUTANTS = {
     "transposed_backsub": ("f[i] -= M[i + k * n] * xk;", "f[i] -= M[k + i * n] * xk;"),
     "multiplier_times": ("M[i + k * n] /= piv;", "M[i + k * n] *= piv;"),
     "no_rhs_swap": ("zc t = F[k + c * n]; F[k + c * n] = F[r + c * n]; F[r + c * n] = t;", ";"),
-    "conj_in_G": ("acc += C[i + k * ldc] * X[k + c * ldx];", "acc += C[i + k * ldc] * conj(X[k + c * ldx]);"),
+    "conj_in_G": ("acc += C[i + k * ldc] * Xj[k + c * ldx];", "acc += C[i + k * ldc] * conj(Xj[k + c * ldx]);"),
+    "transpose_ignored": ("trans ? A[j + i * lda] : A[i + j * lda]", "A[i + j * lda]"),
+    "rhs_leg_reads_B": ("F0 ? F0[i + c * ldf] : B[i + c * ldb]", "F0 ? F0[i + c * ldf] * 0.5 : B[i + c * ldb]"),
     "backsub_no_divide": ("zc xk = f[k] / M[k + k * n];", "zc xk = f[k];"),
     "trailing_off_by_one": ("for (int64_t i = k + 1; i <= last; ++i) M[i + j * n]",
                             "for (int64_t i = k + 1; i < last; ++i) M[i + j * n]"),
@@ -38,7 +40,7 @@ def _pins_pass(lib) -> bool:
     B = rng.standard_normal((n, m))
     C = rng.standard_normal((p, n))
     shifts = np.array([0.4j, -1.0 + 2.0j])
-    X, G, _, _ = oracle.solve(np.diag(a), B, C, shifts, lib=lib)
+    X, G, _ = oracle.solve(np.diag(a), B, C, shifts, lib=lib)
     for j, sg in enumerate(shifts):
         Xc = B / (a - sg)[:, None]
         if oracle.forward_error(X[:, j * m:(j + 1) * m], Xc) > 1e-13:
@@ -47,7 +49,7 @@ def _pins_pass(lib) -> bool:
             return False
     # dense system against LAPACK (library routine)
     A, B, C = workloads.system(30, 2, 2, 17)
-    X, G, _, _ = oracle.solve(A, B, C, shifts, lib=lib)
+    X, G, _ = oracle.solve(A, B, C, shifts, lib=lib)
     for j, sg in enumerate(shifts):
         Xl = np.linalg.solve(A - sg * np.eye(30), B.astype(complex))
         if not np.isfinite(X).all() or oracle.forward_error(X[:, j * m:(j + 1) * m], Xl) > 1e-12:
@@ -61,10 +63,20 @@ def _pins_pass(lib) -> bool:
     np.fill_diagonal(A, 0.0)
     B = rng.standard_normal((n, 2))
     C = rng.standard_normal((1, n))
-    X, _, _, _ = oracle.solve(A, B, C, np.array([0.01j]), lib=lib)
+    X, _, _ = oracle.solve(A, B, C, np.array([0.01j]), lib=lib)
     Xl = np.linalg.solve(A - 0.01j * np.eye(n), B.astype(complex))
     if not np.isfinite(X).all() or oracle.forward_error(X, Xl) > 1e-12:
         return False
+    # per-shift right-hand sides, plain and transposed, against LAPACK
+    A, _, _ = workloads.system(30, 1, 1, 18)
+    F = rng.standard_normal((30, 2)) + 1j * rng.standard_normal((30, 2))
+    for trans in (False, True):
+        X, _ = oracle.solve_rhs(A, F, shifts, 1, trans=trans, lib=lib)
+        op = A.T if trans else A
+        for j, sg in enumerate(shifts):
+            xl = np.linalg.solve(op - sg * np.eye(30), F[:, j])
+            if not np.isfinite(X).all() or oracle.forward_error(X[:, j], xl) > 1e-12:
+                return False
     return True
 
 

@@ -127,3 +127,47 @@ def request_stream(count: int, rate_hz: float, n_systems: int = 8, seed: int = A
         mode = "fp64" if rng.random() < 0.5 else "mixed"
         out.append((t, sys_id, shifts, mode))
     return out
+
+
+@dataclasses.dataclass
+class ModalSystem:
+    """A = U D U^T with D block diagonal (1 x 1 blocks d and 2 x 2 rotation
+    blocks [[al, be], [-be, al]]) and U = P_k ... P_1 a product of k
+    Householder reflectors P_i = I - 2 v_i v_i^T (unit v_i, column i-1 of V),
+    so the spectrum is known exactly and U is cheap to apply."""
+    A: np.ndarray
+    B: np.ndarray
+    C: np.ndarray
+    V: np.ndarray              # n x k, unit columns v_i
+    blocks: list               # (first index, size 1 or 2, al, be)
+
+
+def modal_system(n: int, m: int, p: int, seed: int, k: int = 4) -> ModalSystem:
+    """A modal test system of order n with eigenvalues in the left half plane
+    (al in [-2.5, -0.5], be in [0.2, 1.0]), B and C with N(0, 1) entries."""
+    rng = np.random.default_rng(seed)
+    blocks = []
+    D = np.zeros((n, n))
+    i = 0
+    while i < n:
+        if i + 1 < n and rng.random() < 0.5:
+            al, be = -1.5 + rng.uniform(-1.0, 1.0), rng.uniform(0.2, 1.0)
+            D[i, i] = D[i + 1, i + 1] = al
+            D[i, i + 1], D[i + 1, i] = be, -be
+            blocks.append((i, 2, al, be))
+            i += 2
+        else:
+            d = -1.5 + rng.uniform(-1.0, 1.0)
+            D[i, i] = d
+            blocks.append((i, 1, d, 0.0))
+            i += 1
+    V = rng.standard_normal((n, k))
+    V /= np.linalg.norm(V, axis=0)[None, :]
+    A = D
+    for q in range(k):   # A <- P A P with P = I - 2 v v^T: A = P_k ... P_1 D P_1 ... P_k
+        v = V[:, q]
+        A -= 2.0 * np.outer(v, v @ A)
+        A -= 2.0 * np.outer(A @ v, v)
+    B = rng.standard_normal((n, m))
+    C = rng.standard_normal((p, n))
+    return ModalSystem(np.asfortranarray(A), np.asfortranarray(B), np.asfortranarray(C), V, blocks)

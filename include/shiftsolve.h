@@ -183,6 +183,46 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts,
               double *eta, int32_t *status, void *stream);
 
 /*
+ * Transposed systems with unstructured right-hand sides (Section 3.3, the
+ * second family of systems of the interpolation method; Algorithm 11 and its
+ * continuation): solve
+ *
+ *     (H - sigma_j I)^T Y_j = D_j,   j = 0 .. s-1,
+ *
+ * in reduced coordinates (for (A - sigma I)^T x = c take D = Q^T c, e.g.
+ * D = Ct^T c_hat for c = C^T c_hat; then x = Q Y, shs_apply_q).  The
+ * transpose is the plain one, not the conjugate transpose.  The matrix
+ * (H - sigma I)^T is lower m-Hessenberg; it is factored top-down,
+ * (H - sigma I)^T = L Q_sigma, with the forward substitution for L fused
+ * into the factorisation, and Y = Q_sigma^* (L^{-1} D) formed afterwards
+ * from the stored reflectors.  The library carries this out as the
+ * bottom-up RQ sweep of J H^T J - sigma I (J the order-reversing permutation;
+ * J H^T J is upper m-Hessenberg) on the reversed right-hand sides, which is
+ * the same factorisation in reversed index order; J H^T J is built on the
+ * first transposed solve and kept by the handle (n^2 doubles).
+ *
+ *   shifts   device, s complex.
+ *   r        right-hand sides per shift, r >= 1 (processed in groups of m).
+ *   D, ldd   device, n x (s*r) complex, D(:, j*r:(j+1)*r) = D_j; read only.
+ *   outputs  SHS_OUT_X and/or SHS_OUT_ETA.
+ *   work     device workspace of shs_solve_transposed_workspace(h, s, r)
+ *            bytes, or NULL (allocated on the stream).
+ *   X, ldx   device, n x (s*r) complex, laid out as D (with SHS_OUT_X).
+ *   eta      device, s doubles (with SHS_OUT_ETA): the normwise backward
+ *            error of the transposed system, max over the shift's columns of
+ *            ||r_c||_inf / (||(H - sigma I)^T||_inf ||y_c||_inf + ||d_c||_inf),
+ *            r = D_j - (H - sigma_j I)^T Y_j in FP64.
+ *   status   device, s int32 SHS_STATUS_* (OK, SINGULAR, NONFINITE).
+ *
+ * FP64 throughout.  Asynchronous on `stream` (the first call on a handle
+ * allocates J H^T J with hipMalloc).  Errors as shs_solve.
+ */
+int shs_solve_transposed_workspace(const shs_handle *h, int64_t s, int64_t r, size_t *bytes);
+int shs_solve_transposed(shs_handle *h, int64_t s, const double *shifts, int64_t r,
+                         const double *D, int64_t ldd, int outputs, void *work, size_t work_bytes,
+                         double *X, int64_t ldx, double *eta, int32_t *status, void *stream);
+
+/*
  * X_orig = Q X_red: maps ncols reduced-coordinate columns (complex, device,
  * n x ncols, leading dimension ld) to A's coordinates (device, ldo), where
  * X_orig = (A - sigma I)^{-1} B for a solution X_red of the reduced system

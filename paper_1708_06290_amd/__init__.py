@@ -21,9 +21,11 @@ from ._lib import (SHS_ERR_CANCELLED, SHS_ERR_STATE, SHS_MAX_M, SHS_MODE_FP32_RE
                    shs_get_reduced, shs_info, shs_last_timings, shs_reduce, shs_server_cancel, shs_server_clock,
                    shs_server_create, shs_server_destroy, shs_server_latency, shs_server_pause, shs_server_poll,
                    shs_server_register, shs_server_stats, shs_server_submit, shs_server_submit_ex,
-                   shs_server_wait, shs_set_timing, shs_solve, shs_solve_workspace)
+                   shs_server_wait, shs_set_timing, shs_solve, shs_solve_transposed,
+                   shs_solve_transposed_workspace, shs_solve_workspace)
 
 __all__ = ["System", "SolveResult", "library", "shs_reduce", "shs_solve", "shs_solve_workspace",
+           "shs_solve_transposed", "shs_solve_transposed_workspace",
            "shs_apply_q", "shs_get_reduced", "shs_info", "shs_set_timing", "shs_last_timings",
            "shs_destroy", "ShsError", "Server", "Request", "shs_server_create", "shs_server_register",
            "shs_server_submit", "shs_server_submit_ex", "shs_server_poll", "shs_server_wait", "shs_server_latency",
@@ -114,6 +116,22 @@ class System:
         X = Xs.t() if Xs is not None else None
         G = Gs.t()[:p] if Gs is not None else None
         return SolveResult(X, G, eta, status)
+
+    def solve_transposed(self, shifts, D, r=None, outputs=SHS_OUT_X | SHS_OUT_ETA, stream=None):
+        """(H - sigma_j I)^T Y_j = D_j for an (n, s*r) complex tensor D (reduced
+        coordinates); returns a :class:`SolveResult` with X = Y and G None."""
+        import torch
+        shifts = torch.as_tensor(shifts, dtype=torch.complex128, device=self.device).reshape(-1).contiguous()
+        s = shifts.numel()
+        D = torch.as_tensor(D, dtype=torch.complex128, device=self.device)
+        if r is None:
+            r = D.shape[1] // max(s, 1)
+        Ds = D.t().contiguous()
+        Xs = torch.empty_like(Ds) if outputs & SHS_OUT_X else None
+        eta = torch.empty(s, dtype=torch.float64, device=self.device) if outputs & SHS_OUT_ETA else None
+        status = torch.empty(s, dtype=torch.int32, device=self.device)
+        shs_solve_transposed(self.handle, shifts, r, Ds, Xs, eta, status, outputs=outputs, stream=stream)
+        return SolveResult(Xs.t() if Xs is not None else None, None, eta, status)
 
     def apply_q(self, X, stream=None):
         """Q X for an (n, k) complex128 tensor of reduced-coordinate columns."""

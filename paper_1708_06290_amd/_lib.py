@@ -34,7 +34,8 @@ EXPORTED = ("shs_reduce", "shs_solve_workspace", "shs_solve", "shs_apply_q", "sh
             "shs_abi_version", "shs_server_create", "shs_server_register", "shs_server_submit",
             "shs_server_poll", "shs_server_wait", "shs_server_latency", "shs_server_stats",
             "shs_server_destroy", "shs_server_submit_ex", "shs_server_cancel", "shs_server_pause",
-            "shs_server_clock")
+            "shs_server_clock", "shs_reduce_check_plan", "shs_solve_transposed",
+            "shs_solve_transposed_workspace")
 
 _lib = None
 
@@ -102,6 +103,13 @@ def _load():
     lib.shs_solve.argtypes = [vp, i64, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                               vp, ctypes.c_size_t, dp, i64, dp, i64, dp, vp, vp]
     lib.shs_solve.restype = ctypes.c_int
+    lib.shs_solve_transposed_workspace.argtypes = [vp, i64, i64, ctypes.POINTER(ctypes.c_size_t)]
+    lib.shs_solve_transposed_workspace.restype = ctypes.c_int
+    lib.shs_solve_transposed.argtypes = [vp, i64, dp, i64, dp, i64, ctypes.c_int, vp, ctypes.c_size_t, dp, i64, dp,
+                                         vp, vp]
+    lib.shs_solve_transposed.restype = ctypes.c_int
+    lib.shs_reduce_check_plan.argtypes = [i64, i64, i64, ctypes.POINTER(i64), ctypes.c_char_p, i64]
+    lib.shs_reduce_check_plan.restype = ctypes.c_int
     lib.shs_apply_q.argtypes = [vp, i64, dp, i64, dp, i64, vp]
     lib.shs_apply_q.restype = ctypes.c_int
     lib.shs_get_reduced.argtypes = [vp, dp, i64, dp, i64, dp, i64, vp]
@@ -226,6 +234,32 @@ def shs_solve(h, shifts, X, G, eta, status, mode=SHS_MODE_FP64, outputs=SHS_OUT_
     rc = lib.shs_solve(h, s, _ptr(shifts), mode, outputs, tol, max_iter, wptr, wbytes,
                        _ptr(X), ldx, _ptr(G), ldg, _ptr(eta), _ptr(status), _stream(stream))
     _check("shs_solve", rc)
+
+
+def shs_solve_transposed_workspace(h, s, r):
+    b = ctypes.c_size_t()
+    _check("shs_solve_transposed_workspace", _load().shs_solve_transposed_workspace(h, s, r, ctypes.byref(b)))
+    return b.value
+
+
+def shs_solve_transposed(h, shifts, r, D, X, eta, status, outputs=SHS_OUT_X | SHS_OUT_ETA, work=None, stream=None):
+    """(H - sigma_j I)^T Y_j = D_j; ``D`` and ``X`` are (s*r, n) complex128
+    tensors (column-major n x (s*r)), ``eta`` (s,) float64, ``status`` (s,) int32."""
+    lib = _load()
+    s = shifts.numel()
+    wptr, wbytes = (_ptr(work), work.numel() * work.element_size()) if work is not None else (None, 0)
+    ldx = X.shape[1] if X is not None else 1
+    rc = lib.shs_solve_transposed(h, s, _ptr(shifts), r, _ptr(D), D.shape[1], outputs, wptr, wbytes, _ptr(X), ldx,
+                                  _ptr(eta), _ptr(status), _stream(stream))
+    _check("shs_solve_transposed", rc)
+
+
+def shs_reduce_check_plan(n, m, p):
+    """Host-only dry run of the reduction's launch plan: (violations, launches, first message)."""
+    launches = ctypes.c_int64()
+    msg = ctypes.create_string_buffer(256)
+    rc = _load().shs_reduce_check_plan(n, m, p, ctypes.byref(launches), msg, 256)
+    return rc, launches.value, msg.value.decode()
 
 
 def shs_apply_q(h, Xred, Xorig, stream=None):

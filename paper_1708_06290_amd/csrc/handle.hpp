@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "shiftsolve.h"
@@ -36,11 +37,30 @@ struct shs_handle {
     bool last_mixed = false;   // the last timed solve ran the mixed mode
     double tile_flops = 0.0, update_flops = 0.0;   // algorithmic flops of the blocked sweep's launches
     long long *dstats = nullptr;   // device counters of the mixed mode's last timed solve (3 values)
+    // transposed systems: Ht = J H^T J (J the order-reversing permutation) is
+    // upper m-Hessenberg; built on the first transposed solve
+    double *Ht = nullptr, *ht_offrow = nullptr, *ht_diag = nullptr;
+    hipEvent_t ht_ready = nullptr;
+    std::mutex ht_mu;
 };
 
 enum { PH_SWEEP = 0, PH_QSTAR, PH_RESIDUAL, PH_SWEEP32, PH_SWEEP32D, PH_OTHER, PH_TILE, PH_UPDATE, PH_COUNT };
 
 namespace shs {
+
+// Variants of the certification (all fields optional): another matrix of the
+// same order and band (with its off-diagonal row sums and diagonal for
+// ||M - sigma I||_inf), nc solution columns per shift instead of m, and dense
+// complex right-hand sides E (column sid nc + c at E + col lde * 2) instead
+// of [R; 0], with a per-column scratch emax for their maxima.
+struct CertifyOpts {
+    const double *H = nullptr;
+    const double *offrow = nullptr, *diag = nullptr;
+    int nc = 0;
+    const double *E = nullptr;
+    int64_t lde = 0;
+    unsigned long long *emax = nullptr;
+};
 
 // FP64 residual R - (H X - sigma X) and backward error of the listed shifts
 // (dlist == nullptr: shifts 0 .. s_list-1; dcount set: the list's length is
@@ -48,7 +68,13 @@ namespace shs {
 // resmax/xmax are per-column scratch of m * s_total entries.
 hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const int *dcount, const double *shifts,
                    const double *X, int64_t ldx, double *Res, unsigned long long *resmax, unsigned long long *xmax,
-                   double *eta, int32_t *status, int64_t s_total, double *Xt, hipStream_t st);
+                   double *eta, int32_t *status, int64_t s_total, double *Xt, hipStream_t st,
+                   const CertifyOpts *opt = nullptr);
+
+// Zero `bytes` bytes (a multiple of 8) at p with a kernel on st: the solve
+// path clears its scratch this way rather than with hipMemsetAsync, so a
+// solve can be recorded into a HIP graph and replayed.
+hipError_t zero_fill(void *p, size_t bytes, hipStream_t st);
 
 // G(:, j*m + c) = Ct X(:, j*m + c) for shifts 0 .. s-1.
 hipError_t g_eval(shs_handle *h, int64_t s, const double *X, int64_t ldx, double *G, int64_t ldg, hipStream_t st);

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -44,6 +45,10 @@ void free_handle(shs_handle *h)
     hipFree(h->offrow);
     hipFree(h->diag);
     hipFree(h->dstats);
+    hipFree(h->Ht);
+    hipFree(h->ht_offrow);
+    hipFree(h->ht_diag);
+    if (h->ht_ready) hipEventDestroy(h->ht_ready);
     delete h;
 }
 
@@ -334,13 +339,13 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     // columns past 2m of each shift, those of the padding shifts and the
     // rows past the bottom tile's K stay zero.  Bm is row-major with row
     // stride ncols.
-    hipError_t e = hipMemsetAsync(Bm, 0, sizeof(double) * L.blk_rows * ncols, st);
+    hipError_t e = zero_fill(Bm, sizeof(double) * L.blk_rows * ncols, st);
     if (e != hipSuccess) return e;
-    e = hipMemsetAsync(M2, 0, sizeof(double) * (ncols / w) * w * w, st);
+    e = zero_fill(M2, sizeof(double) * (ncols / w) * w * w, st);
     if (e != hipSuccess) return e;
-    e = hipMemsetAsync(M2p, 0, sizeof(double) * (ncols / w) * w * w, st);
+    e = zero_fill(M2p, sizeof(double) * (ncols / w) * w * w, st);
     if (e != hipSuccess) return e;
-    e = hipMemsetAsync(M2q, 0, sizeof(double) * (ncols / w) * w * w, st);
+    e = zero_fill(M2q, sizeof(double) * (ncols / w) * w * w, st);
     if (e != hipSuccess) return e;
     BlkTriArgs ta{};
     ta.n = n;
@@ -495,56 +500,256 @@ hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const 
     return hipGetLastError();
 }
 
+// ---- transposed systems (H - sigma I)^T Y = D -----------------------------
+// With J the order-reversing permutation, J (H - sigma I)^T J = Ht - sigma I
+// where Ht = J H^T J, Ht(i, j) = H(n-1-j, n-1-i), is upper m-Hessenberg again:
+// (H - sigma I)^T Y = D  <=>  (Ht - sigma I) (J Y) = J D.  The bottom-up RQ
+// sweep of Ht - sigma I with the right-hand side J D is the top-down LQ
+// factorisation (H - sigma I)^T = L Q of Section 3.3, with the forward
+// substitution for L fused into it, in reversed index order.
+
+// Ht = J H^T J through 64 x 64 LDS tiles: loads along the columns of H,
+// stores along the columns of Ht.
+__global__ __launch_bounds__(256) void transpose_reverse_kernel(int n, const double *H, int64_t ldh, double *Ht)
+{
+    __shared__ double t[64][65];
+    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;   // Ht rows i0.., columns j0..
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    // Ht(i, j) = H(n-1-j, n-1-i): rows r = n-1-j of H, columns c = n-1-i
+    for (int q = ty; q < 64; q += 4) {
+        const int i = i0 + q, j = j0 + tx;
+        t[q][tx] = (i < n && j < n) ? H[(int64_t)(n - 1 - i) * ldh + (n - 1 - j)] : 0.0;
+    }
+    __syncthreads();
+    for (int q = ty; q < 64; q += 4) {
+        const int j = j0 + q, i = i0 + tx;
+        if (i < n && j < n) Ht[(int64_t)j * ldh + i] = t[tx][q];
+    }
+}
+
+// Off-diagonal row sums and diagonal of Ht: row i of Ht is column n-1-i of H.
+__global__ __launch_bounds__(256) void ht_norms_kernel(int n, const double *H, int64_t ldh, double *offrow,
+                                                       double *diag)
+{
+    const int i = blockIdx.x, c = n - 1 - i;
+    const double *col = H + (int64_t)c * ldh;
+    double acc = 0.0;
+    for (int r = threadIdx.x; r < n; r += 256) acc += r == c ? 0.0 : fabs(col[r]);
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        offrow[i] = red[0];
+        diag[i] = col[c];
+    }
+}
+
+// Build Ht and its norms on the first transposed solve (kept by the handle);
+// every solve's stream then waits for them.
+hipError_t ensure_transposed(shs_handle *h, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(h->ht_mu);
+    if (!h->Ht) {
+        const int64_t n = h->n;
+        double *Ht = nullptr, *off = nullptr, *dg = nullptr;
+        hipError_t e = hipMalloc((void **)&Ht, sizeof(double) * h->ldh * n);
+        if (e == hipSuccess) e = hipMalloc((void **)&off, sizeof(double) * n);
+        if (e == hipSuccess) e = hipMalloc((void **)&dg, sizeof(double) * n);
+        if (e == hipSuccess && !h->ht_ready) e = hipEventCreateWithFlags(&h->ht_ready, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMemsetAsync(Ht, 0, sizeof(double) * h->ldh * n, st);   // padding rows
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(transpose_reverse_kernel, dim3(cdiv(n, 64), cdiv(n, 64)), dim3(256), 0, st, (int)n,
+                               (const double *)h->H, h->ldh, Ht);
+            hipLaunchKernelGGL(ht_norms_kernel, dim3((unsigned)n), dim3(256), 0, st, (int)n, (const double *)h->H,
+                               h->ldh, off, dg);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(h->ht_ready, st);
+        if (e != hipSuccess) {
+            hipFree(Ht);
+            hipFree(off);
+            hipFree(dg);
+            return e;
+        }
+        h->Ht = Ht;
+        h->ht_offrow = off;
+        h->ht_diag = dg;
+        h->resident += sizeof(double) * (h->ldh * n + 2 * n);
+        return hipSuccess;
+    }
+    return hipStreamWaitEvent(st, h->ht_ready, 0);
+}
+
+// Virtual items v = j nch + q (shift j, chunk q of m right-hand sides):
+// their shifts, and E_v(i, c) = D(n-1-i, j r + q m + c) (zero past column r).
+__global__ __launch_bounds__(256) void transposed_pack_kernel(int n, int m, int r, int nch, const double *shifts,
+                                                              const double *D, int64_t ldd, double *shv, double *E)
+{
+    const int v = blockIdx.x, j = v / nch, q = v % nch;
+    if (blockIdx.y == 0 && threadIdx.x < 2) shv[2 * v + threadIdx.x] = shifts[2 * j + threadIdx.x];
+    const int64_t total = (int64_t)n * m;
+    for (int64_t idx = (int64_t)blockIdx.y * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.y * 256) {
+        const int c = (int)(idx / n), i = (int)(idx % n), k = q * m + c;
+        double re = 0.0, im = 0.0;
+        if (k < r) {
+            const double *p = D + (((int64_t)j * r + k) * ldd + (n - 1 - i)) * 2;
+            re = p[0];
+            im = p[1];
+        }
+        double *e = E + (((int64_t)v * m + c) * n + i) * 2;
+        e[0] = re;
+        e[1] = im;
+    }
+}
+
+// X(i, j r + k) = Xv(n-1-i, v m + c) with k = q m + c < r; per shift, eta is
+// the largest of its items' and the status the first non-OK one.
+__global__ __launch_bounds__(256) void transposed_unpack_kernel(int n, int m, int r, int nch, const double *Xv,
+                                                                double *X, int64_t ldx, const double *etav,
+                                                                const int32_t *stv, double *eta, int32_t *status)
+{
+    const int v = blockIdx.x, j = v / nch, q = v % nch;
+    if (q == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        int st = 0;
+        double e = 0.0;
+        for (int qq = 0; qq < nch; ++qq) {
+            const int s2 = stv[j * nch + qq];
+            if (st == 0) st = s2;
+            if (etav) {
+                const double x = etav[j * nch + qq];
+                e = (x > e || x != x) ? x : e;
+            }
+        }
+        status[j] = st;
+        if (eta && etav) eta[j] = e;
+    }
+    if (!X) return;
+    const int cols = min(m, r - q * m);
+    const int64_t total = (int64_t)n * cols;
+    for (int64_t idx = (int64_t)blockIdx.y * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.y * 256) {
+        const int c = (int)(idx / n), i = (int)(idx % n);
+        const double *p = Xv + (((int64_t)v * m + c) * n + (n - 1 - i)) * 2;
+        double *o = X + (((int64_t)j * r + q * m + c) * ldx + i) * 2;
+        o[0] = p[0];
+        o[1] = p[1];
+    }
+}
+
+struct TransLayout {
+    size_t shv = 0, e = 0, yd = 0, refl = 0, xv = 0, stv = 0, etav = 0, resmax = 0, xmax = 0, emax = 0, xt = 0;
+    size_t total = 0;
+    int64_t nch = 0, nv = 0, refl_stride = 0;
+};
+
+bool trans_layout(const shs_handle *h, int64_t s, int64_t r, TransLayout *L)
+{
+    const int64_t n = h->n, m = h->m;
+    Geo g;
+    if (!geo(false, n, m, true, &g)) return false;
+    L->nch = (r + m - 1) / m;
+    L->nv = s * L->nch;
+    L->refl_stride = g.stride;
+    const int64_t nv = L->nv;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += al(bytes); return o; };
+    L->shv = take(sizeof(double) * 2 * nv);
+    L->e = take(sizeof(double) * 2 * n * m * nv);
+    L->yd = take(sizeof(double) * 2 * n * m * nv);
+    L->refl = take(sizeof(double) * g.stride * nv);
+    L->xv = take(sizeof(double) * 2 * n * m * nv);
+    L->stv = take(sizeof(int32_t) * nv);
+    L->etav = take(sizeof(double) * nv);
+    L->resmax = take(sizeof(unsigned long long) * m * nv);
+    L->xmax = take(sizeof(unsigned long long) * m * nv);
+    L->emax = take(sizeof(unsigned long long) * m * nv);
+    L->xt = take(sizeof(double) * residual_pack_rows(n) * residual_pack_ld(m * nv));
+    L->total = off;
+    return true;
+}
+
 }  // namespace
 
 namespace shs {
 
+__global__ __launch_bounds__(256) void zero_fill_kernel(unsigned long long *p, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) p[i] = 0ull;
+}
+
+hipError_t zero_fill(void *p, size_t bytes, hipStream_t st)
+{
+    const int64_t count = (int64_t)(bytes / 8);
+    if (count <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<int64_t>((count + 255) / 256, 8192);
+    hipLaunchKernelGGL(zero_fill_kernel, dim3(grid), dim3(256), 0, st, (unsigned long long *)p, count);
+    return hipGetLastError();
+}
+
 // residual + eta for the listed shifts; Res optional.
 hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const int *dcount, const double *shifts,
                    const double *X, int64_t ldx, double *Res, unsigned long long *resmax, unsigned long long *xmax,
-                   double *eta, int32_t *status, int64_t s_total, double *Xt, hipStream_t st)
+                   double *eta, int32_t *status, int64_t s_total, double *Xt, hipStream_t st, const CertifyOpts *opt)
 {
+    const CertifyOpts none;
+    if (!opt) opt = &none;
     const int64_t n = h->n, m = h->m;
+    const int64_t nc = opt->nc > 0 ? opt->nc : m;
+    const double *Hm = opt->H ? opt->H : h->H;
     // timed phases: the residual GEMM alone; clearing, packing and eta count
     // as other work
     PhaseScope ps0(h, PH_OTHER, s_list, st);
-    hipError_t e = hipMemsetAsync(resmax, 0, sizeof(unsigned long long) * m * s_total, st);
+    hipError_t e = zero_fill(resmax, sizeof(unsigned long long) * nc * s_total, st);
     if (e != hipSuccess) return e;
-    e = hipMemsetAsync(xmax, 0, sizeof(unsigned long long) * m * s_total, st);
+    e = zero_fill(xmax, sizeof(unsigned long long) * nc * s_total, st);
     if (e != hipSuccess) return e;
+    if (opt->E) {
+        e = zero_fill(opt->emax, sizeof(unsigned long long) * nc * s_total, st);
+        if (e != hipSuccess) return e;
+    }
     ResidualArgs ra;
     ra.n = (int)n;
     ra.m = (int)m;
+    ra.nc = (int)nc;
     ra.count = (int)s_list;
     ra.list = dlist;
-    ra.H = h->H;
+    ra.H = Hm;
     ra.ldh = h->ldh;
     ra.Rtop = h->Rtop;
     ra.shifts = shifts;
     ra.X = X;
     ra.ldx = ldx;
     ra.Xt = Xt;
-    ra.ldxt = residual_pack_ld(s_list * m);
     ra.Res = Res;
     ra.ldr = n;
     ra.resmax = resmax;
     ra.xmax = xmax;
     ra.dcount = dcount;
+    ra.E = opt->E;
+    ra.lde = opt->lde;
+    ra.emax = opt->emax;
+    ra.ldxt = residual_pack_ld(s_list * nc);
     if (s_list <= 0) return hipGetLastError();
     // what the direct-to-LDS loads assume: 16-byte aligned pairs of rows
-    if (n < 2 || h->ldh & 1 || ((uintptr_t)h->H | (uintptr_t)Xt) & 15) return hipErrorInvalidValue;
+    if (n < 2 || h->ldh & 1 || ((uintptr_t)Hm | (uintptr_t)Xt) & 15) return hipErrorInvalidValue;
+    if (!opt->E && nc != m) return hipErrorInvalidValue;
     hipLaunchKernelGGL(residual_pack_kernel, dim3(cdiv(residual_pack_rows(n), 64), ra.ldxt / 64), dim3(256), 0, st,
                        ra);
     ps0.end();
     {
         PhaseScope ps(h, PH_RESIDUAL, s_list, st);
-        hipLaunchKernelGGL(residual_mfma_kernel, dim3(cdiv(n, 128), cdiv(s_list * m, 64)), dim3(256), kResidualLds,
+        hipLaunchKernelGGL(residual_mfma_kernel, dim3(cdiv(n, 128), cdiv(s_list * nc, 64)), dim3(256), kResidualLds,
                            st, ra);
     }
     PhaseScope ps1(h, PH_OTHER, s_list, st);
-    hipLaunchKernelGGL(eta_kernel, dim3((unsigned)s_list), dim3(256), 0, st, (int)n, (int)m, (int)s_list, dcount, dlist,
-                       shifts, (const double *)h->offrow, (const double *)h->diag, (const double *)h->rcolmax,
-                       (const unsigned long long *)resmax, (const unsigned long long *)xmax, eta, status);
+    hipLaunchKernelGGL(eta_kernel, dim3((unsigned)s_list), dim3(256), 0, st, (int)n, (int)nc, (int)s_list, dcount, dlist,
+                       shifts, opt->offrow ? opt->offrow : (const double *)h->offrow,
+                       opt->diag ? opt->diag : (const double *)h->diag, (const double *)h->rcolmax,
+                       (const unsigned long long *)resmax, (const unsigned long long *)xmax,
+                       (const unsigned long long *)opt->emax, eta, status);
     return hipGetLastError();
 }
 
@@ -1134,6 +1339,129 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outp
     }
     if (e != hipSuccess) rc = (e == hipErrorOutOfMemory) ? SHS_ERR_NOMEM : SHS_ERR_HIP;
     return rc;
+}
+
+int shs_solve_transposed_workspace(const shs_handle *h, int64_t s, int64_t r, size_t *bytes)
+{
+    if (!h) return -1;
+    if (s < 0) return -2;
+    if (r < 1) return -3;
+    if (!bytes) return -4;
+    TransLayout L;
+    if (!trans_layout(h, s, r, &L)) return SHS_ERR_UNSUPPORTED;
+    *bytes = L.total;
+    return 0;
+}
+
+int shs_solve_transposed(shs_handle *h, int64_t s, const double *shifts, int64_t r, const double *D, int64_t ldd,
+                         int outputs, void *work, size_t work_bytes, double *X, int64_t ldx, double *eta,
+                         int32_t *status, void *stream)
+{
+    if (!h) return -1;
+    if (s < 0) return -2;
+    if (s > 0 && !shifts) return -3;
+    if (r < 1) return -4;
+    if (s > 0 && !D) return -5;
+    if (ldd < h->n) return -6;
+    if (!(outputs & SHS_OUT_X) && !(outputs & SHS_OUT_ETA)) return -7;
+    if (outputs & ~(SHS_OUT_X | SHS_OUT_ETA)) return -7;
+    if (s == 0) return 0;
+    if ((outputs & SHS_OUT_X) && (!X || ldx < h->n)) return -10;
+    if ((outputs & SHS_OUT_ETA) && !eta) return -12;
+    if (!status) return -13;
+    const int64_t n = h->n, m = h->m;
+    TransLayout L;
+    if (!trans_layout(h, s, r, &L)) return SHS_ERR_UNSUPPORTED;
+    if (L.nv > INT32_MAX / 64) return -2;
+    hipStream_t st = (hipStream_t)stream;
+    bool owned = false;
+    if (work) {
+        if (work_bytes < L.total) return -9;
+    } else {
+        RETURN_IF_HIP(hipMallocAsync(&work, L.total, st));
+        owned = true;
+    }
+    hipError_t e = ensure_transposed(h, st);
+    const int nv = (int)L.nv;
+    double *shv = at<double>(work, L.shv), *E = at<double>(work, L.e), *Xv = at<double>(work, L.xv);
+    int32_t *stv = at<int32_t>(work, L.stv);
+    double *etav = at<double>(work, L.etav);
+    const unsigned chunks = std::max<unsigned>(1, std::min<unsigned>(64, cdiv(n * m, 256 * 16)));
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(transposed_pack_kernel, dim3((unsigned)nv, chunks), dim3(256), 0, st, (int)n, (int)m,
+                           (int)r, (int)L.nch, shifts, D, ldd, shv, E);
+        e = hipGetLastError();
+    }
+    Geo g;
+    geo(false, n, m, true, &g);
+    if (e == hipSuccess) {
+        SweepArgs<double> da{};
+        da.n = (int)n;
+        da.count = nv;
+        da.H = h->Ht;
+        da.ldh = h->ldh;
+        da.shifts = shv;
+        da.list = nullptr;
+        da.Rtop = h->Rtop;
+        da.E = E;
+        da.e_stride = 2 * n * m;
+        da.refl = at<double>(work, L.refl);
+        da.refl_stride = L.refl_stride;
+        da.Y = at<double>(work, L.yd);
+        da.y_stride = 2 * n * m;
+        da.status = stv;
+        {
+            PhaseScope ps(h, PH_SWEEP, nv, st);
+            if (!launch_sweep((int)m, true, da, st)) e = hipErrorInvalidValue;
+        }
+        QstarArgs<double> dq{};
+        dq.n = (int)n;
+        dq.count = nv;
+        dq.list = nullptr;
+        dq.refl = da.refl;
+        dq.refl_stride = L.refl_stride;
+        dq.tile_rows = g.g.tile_rows;
+        dq.tile_stride = g.g.tile_stride;
+        dq.slot = g.g.slot;
+        dq.Y = da.Y;
+        dq.y_stride = 2 * n * m;
+        dq.X = Xv;
+        dq.ldx = n;
+        dq.accumulate = 0;
+        if (e == hipSuccess) {
+            PhaseScope ps(h, PH_QSTAR, nv, st);
+            if (!launch_qstar((int)m, true, dq, st)) e = hipErrorInvalidValue;
+        }
+        if (e == hipSuccess) e = hipGetLastError();
+    }
+    if (e == hipSuccess && (outputs & SHS_OUT_ETA)) {
+        // eta of the reversed system (Ht - sigma I) Z = J D, which is the
+        // transposed system's: the residuals are J-permutations of each other
+        // and ||Ht - sigma I||_inf = ||(H - sigma I)^T||_inf
+        CertifyOpts co;
+        co.H = h->Ht;
+        co.offrow = h->ht_offrow;
+        co.diag = h->ht_diag;
+        co.nc = (int)m;
+        co.E = E;
+        co.lde = n;
+        co.emax = at<unsigned long long>(work, L.emax);
+        e = certify(h, nv, nullptr, nullptr, shv, Xv, n, nullptr, at<unsigned long long>(work, L.resmax),
+                    at<unsigned long long>(work, L.xmax), etav, stv, nv, at<double>(work, L.xt), st, &co);
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(transposed_unpack_kernel, dim3((unsigned)nv, chunks), dim3(256), 0, st, (int)n, (int)m,
+                           (int)r, (int)L.nch, (const double *)Xv, (outputs & SHS_OUT_X) ? X : nullptr, ldx,
+                           (outputs & SHS_OUT_ETA) ? (const double *)etav : nullptr, (const int32_t *)stv,
+                           (outputs & SHS_OUT_ETA) ? eta : nullptr, status);
+        e = hipGetLastError();
+    }
+    if (owned) {
+        hipError_t e2 = hipFreeAsync(work, st);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return (e == hipErrorOutOfMemory) ? SHS_ERR_NOMEM : SHS_ERR_HIP;
+    return 0;
 }
 
 int shs_apply_q(const shs_handle *h, int64_t ncols, const double *Xred, int64_t ld, double *Xorig, int64_t ldo,

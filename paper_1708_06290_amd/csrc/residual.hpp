@@ -3,6 +3,9 @@
 //   Res(:, j m + c) = R(:, c) - (H X_j(:, c) - sigma_j X_j(:, c))
 //   eta_j = max_c ||Res(:, jm+c)||_inf / (||H - sigma_j I||_inf ||X_j(:, c)||_inf + ||R(:, c)||_inf)
 //
+// or, with a dense right-hand side E (nc columns per shift, complex), the same
+// with E(:, j nc + c) in place of R(:, c) and its own column maxima.
+//
 // The product H X over all shifts is one GEMM of the real n x n matrix H
 // against the stacked complex solutions (real and imaginary parts are two
 // real right-hand sides).  H is m-Hessenberg, so for a block of rows
@@ -17,7 +20,8 @@
 namespace shs {
 
 struct ResidualArgs {
-    int n, m, count;            // count = number of listed shifts
+    int n, m, count;            // count = number of listed shifts; m = H's band (H(i, j) = 0 for i > j + m)
+    int nc;                     // solution columns per shift (m for [R; 0] right-hand sides)
     const int32_t *list;        // item -> shift id (nullptr = identity)
     const double *H;            // n x n, ld ldh (even, rows n .. ldh-1 zero)
     int64_t ldh;
@@ -32,6 +36,9 @@ struct ResidualArgs {
     unsigned long long *resmax; // per column (s m), max |Res| (bits of a non-negative double)
     unsigned long long *xmax;   // per column, max |X|
     const int *dcount;          // if set, the number of listed shifts is read here (count is an upper bound)
+    const double *E;            // if set: dense right-hand sides, complex, column sid nc + c at E + col lde * 2
+    int64_t lde;
+    unsigned long long *emax;   // with E: per column, max |E|
 };
 
 typedef double shs_dbl4 __attribute__((ext_vector_type(4)));
@@ -49,7 +56,8 @@ __global__ __launch_bounds__(256) void residual_pack_kernel(ResidualArgs a)
     __shared__ double tr[TK][TW + 1], ti[TK][TW + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int k0 = blockIdx.x * TK, w0 = blockIdx.y * TW;
-    const int ncols = (a.dcount ? *a.dcount : a.count) * a.m, m = a.m;
+    const int m = a.nc;   // columns per shift
+    const int ncols = (a.dcount ? *a.dcount : a.count) * m;
     double xr[PER], xi[PER];
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
@@ -114,7 +122,8 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
     auto Xs = reinterpret_cast<double (*)[BK][BN]>(res_smem + 2 * BK * BM);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int ncols = (a.dcount ? *a.dcount : a.count) * a.m;
+    const int nc = a.nc;   // columns per shift
+    const int ncols = (a.dcount ? *a.dcount : a.count) * nc;
     const int n = a.n, m = a.m;
     const int i0 = blockIdx.x * BM;
     const int w0 = blockIdx.y * (BN / 2);   // first complex column of the tile
@@ -133,7 +142,7 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const int w = w0 + wc * 32 + nt * 8 + q % 8;
-        const int item = (w < ncols ? w : 0) / m;
+        const int item = (w < ncols ? w : 0) / nc;
         const int sid = a.list ? a.list[item] : item;
         sgr[nt] = a.shifts[2 * sid];
         sgi[nt] = a.shifts[2 * sid + 1];
@@ -216,10 +225,10 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
     for (int nt = 0; nt < 4; ++nt) {
         const int w = w0 + wc * 32 + nt * 8 + q % 8;
         const bool ok = w < ncols;
-        const int item = (ok ? w : 0) / m, c = (ok ? w : 0) % m;
+        const int item = (ok ? w : 0) / nc, c = (ok ? w : 0) % nc;
         const int sid = a.list ? a.list[item] : item;
-        const int64_t col = (int64_t)sid * m + c;
-        double mr = 0.0, mxg = mx[nt];
+        const int64_t col = (int64_t)sid * nc + c;
+        double mr = 0.0, mxg = mx[nt], me = 0.0;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -227,8 +236,16 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
                 const double v = acc[mt][nt][r], o = __shfl_xor(v, 8);
                 const int i = i0 + wr * 64 + mt * 16 + 4 * r + lane / 16;
                 if (ok && re_lane && i < n) {
-                    const double rr = ((i < m) ? a.Rtop[c * m + i] : 0.0) - v;
-                    const double ri = -o;
+                    double er = (i < m) ? a.Rtop[(c < m ? c : 0) * m + i] : 0.0, ei = 0.0;
+                    if (a.E) {
+                        const double *pe = a.E + (col * a.lde + i) * 2;
+                        er = pe[0];
+                        ei = pe[1];
+                        const double ae = hypot(er, ei);
+                        me = (ae > me || ae != ae) ? ae : me;
+                    }
+                    const double rr = er - v;
+                    const double ri = ei - o;
                     if (a.Res) {
                         double *pr = a.Res + (col * a.ldr + i) * 2;
                         pr[0] = rr;
@@ -241,25 +258,31 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
         // lanes l, l+16, l+32, l+48 hold the same column
 #pragma unroll
         for (int off = 16; off < 64; off <<= 1) {
-            const double orr = __shfl_xor(mr, off), oxx = __shfl_xor(mxg, off);
+            const double orr = __shfl_xor(mr, off), oxx = __shfl_xor(mxg, off), oee = __shfl_xor(me, off);
             mr = (orr > mr || orr != orr) ? orr : mr;
             mxg = (oxx > mxg || oxx != oxx) ? oxx : mxg;
+            me = (oee > me || oee != oee) ? oee : me;
         }
         if (lane < 8 && ok) {
             if (mr != mr) mr = __longlong_as_double(0x7ff8000000000000LL);
             if (mxg != mxg) mxg = __longlong_as_double(0x7ff8000000000000LL);
+            if (me != me) me = __longlong_as_double(0x7ff8000000000000LL);
             atomic_max_nonneg(a.resmax + col, mr);
             atomic_max_nonneg(a.xmax + col, mxg);
+            if (a.E) atomic_max_nonneg(a.emax + col, me);
         }
     }
 }
 
 // eta per listed shift; updates status (NaN -> NONFINITE).
+// m: columns per shift; the right-hand side's column maxima come from
+// emax (per column, dense right-hand sides) or rcolmax (per column c of R).
 __global__ __launch_bounds__(256) void eta_kernel(int n, int m, int count, const int *dcount, const int32_t *list,
                                                   const double *shifts, const double *offrow,
                                                   const double *diag, const double *rcolmax,
                                                   const unsigned long long *resmax,
                                                   const unsigned long long *xmax,
+                                                  const unsigned long long *emax,
                                                   double *eta, int32_t *status)
 {
     const int item = blockIdx.x;
@@ -287,9 +310,10 @@ __global__ __launch_bounds__(256) void eta_kernel(int n, int m, int count, const
             const int64_t col = (int64_t)sid * m + c;
             const double rmx = __longlong_as_double((long long)resmax[col]);
             const double xmx = __longlong_as_double((long long)xmax[col]);
-            const double den = nh * xmx + rcolmax[c];
+            const double bmx = emax ? __longlong_as_double((long long)emax[col]) : rcolmax[c];
+            const double den = nh * xmx + bmx;
             double v;
-            if (rmx != rmx || xmx != xmx) { v = rmx + xmx; bad = true; }
+            if (rmx != rmx || xmx != xmx || bmx != bmx) { v = rmx + xmx + bmx; bad = true; }
             else v = den > 0.0 ? rmx / den : (rmx > 0.0 ? __longlong_as_double(0x7ff0000000000000LL) : 0.0);
             e = (v > e || v != v) ? v : e;
         }

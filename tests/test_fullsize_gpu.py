@@ -113,8 +113,9 @@ def test_c3_fp64_and_mixed_full():
     _certified(rmx)          # imaginary-axis shifts: no FP64 fallback
     # mixed against FP64, every shift, relative Frobenius error per shift
     m = wl.m
-    d = (rmx.X - r64.X).abs().square().reshape(wl.s, m, wl.n).sum(dim=(1, 2)).sqrt()
-    ref = r64.X.abs().square().reshape(wl.s, m, wl.n).sum(dim=(1, 2)).sqrt()
+    # X is a view of (s m, n) storage: row j m + c holds column c of shift j
+    d = (rmx.X - r64.X).t().abs().square().reshape(wl.s, m, wl.n).sum(dim=(1, 2)).sqrt()
+    ref = r64.X.t().abs().square().reshape(wl.s, m, wl.n).sum(dim=(1, 2)).sqrt()
     rel = (d / ref).cpu().numpy()
     print(f"mixed vs FP64: max relative difference {rel.max():.3e}", flush=True)
     assert (rel <= FWD_TOL).all(), rel.max()

@@ -223,6 +223,99 @@ int shs_solve_transposed(shs_handle *h, int64_t s, const double *shifts, int64_t
                          double *X, int64_t ldx, double *eta, int32_t *status, void *stream);
 
 /*
+ * Systems with a direction of their own per shift (Section 3.3, the systems
+ * of the interpolation method; Section 2 shows why only m entries of the
+ * right-hand side are nontrivial after the reduction): for j = 0 .. s-1,
+ *
+ *     shs_solve_vec:            (H - sigma_j I) x_j = R b_j,
+ *     shs_solve_transposed_vec: (H - sigma_j I)^T w_j = Ct^T c_j,
+ *
+ * i.e. (A - sigma_j I) Q x_j = B b_j and (A - sigma_j I)^T Q w_j = C^T c_j in
+ * A's coordinates (Q x_j, Q w_j via shs_apply_q).  shs_solve_vec runs the
+ * FP64 structured sweep and ends it as the paper's modification lists:
+ * y_j = R_sigma(1:m,1:m)^{-1} R(1:m,1:m) b_j, x_j = Q_sigma^*(:,1:m) y_j.
+ * shs_solve_transposed_vec forms Ct^T c_j on the device and runs
+ * shs_solve_transposed with one right-hand side per shift.
+ *
+ *   shifts     device, s complex.
+ *   bhat, ldb  device, m x s complex (column j = b_j), ldb >= m; read only.
+ *   chat, ldc  device, p x s complex (column j = c_j), ldc >= max(1, p);
+ *              may be NULL when p == 0.
+ *   outputs    SHS_OUT_X and/or SHS_OUT_ETA.
+ *   work       device workspace of the matching *_workspace bytes, or NULL
+ *              (allocated on the stream).
+ *   X, ldx     device, n x s complex, column j = x_j (resp. w_j).  shs_solve_vec
+ *              needs X even without SHS_OUT_X (the residual reads it).
+ *   eta        device, s doubles (with SHS_OUT_ETA): normwise backward error
+ *              of each shift's system, in FP64, defined as for shs_solve and
+ *              shs_solve_transposed with the shift's own right-hand side.
+ *   status     device, s int32 SHS_STATUS_* (OK, SINGULAR, NONFINITE).
+ *
+ * FP64.  Asynchronous on `stream`.  Errors as shs_solve (-i for argument i).
+ */
+int shs_solve_vec_workspace(const shs_handle *h, int64_t s, size_t *bytes);
+int shs_solve_vec(shs_handle *h, int64_t s, const double *shifts, const double *bhat, int64_t ldb, int outputs,
+                  void *work, size_t work_bytes, double *X, int64_t ldx, double *eta, int32_t *status,
+                  void *stream);
+int shs_solve_transposed_vec_workspace(const shs_handle *h, int64_t s, size_t *bytes);
+int shs_solve_transposed_vec(shs_handle *h, int64_t s, const double *shifts, const double *chat, int64_t ldc,
+                             int outputs, void *work, size_t work_bytes, double *X, int64_t ldx, double *eta,
+                             int32_t *status, void *stream);
+
+/*
+ * Petrov-Galerkin projection for the interpolation method (Section 1, the
+ * spaces V_k, W_k; Section 2: in reduced coordinates W^T A V - lambda W^T V =
+ * What^T H Vhat - lambda What^T Vhat, and orthogonalising Vhat, What is the
+ * same as orthogonalising V_k, W_k).  From complex bases V, W (n x r each,
+ * e.g. the outputs of shs_solve_vec and shs_solve_transposed_vec) the call
+ *
+ *   1. forms real bases: column k of Vr is the real part (sel[k] even) or the
+ *      imaginary part (sel[k] odd) of column sel[k] / 2 of V, likewise Wr
+ *      (a conjugate pair of points contributes the real and the imaginary
+ *      part of one of its columns);
+ *   2. orthonormalises Vr and Wr (Gram-Schmidt with reorthogonalisation);
+ *   3. writes Ar = Wr^T H Vr, Er = Wr^T Vr (r x r), Br = Wr^T R (r x m) and
+ *      Cr = Ct Vr (p x r), column-major with leading dimensions r, r, r, p.
+ *
+ *   V, ldv / W, ldw  device, n x r complex, ld >= n; read only.
+ *   sel              device, r int32 (0 <= sel[k] < 2r).
+ *   work             device workspace of shs_project_workspace(h, r) bytes,
+ *                    or NULL (allocated on the stream).
+ *   Ar, Er, Br, Cr   device outputs (Cr may be NULL when p == 0).
+ *   rank_def         device, one int32: set to 1 if a basis column vanished
+ *                    in the orthogonalisation (it is then zero), else 0.
+ *
+ * FP64, asynchronous on `stream`.  Errors: -i for argument i, SHS_ERR_NOMEM,
+ * SHS_ERR_HIP.
+ */
+int shs_project_workspace(const shs_handle *h, int64_t r, size_t *bytes);
+int shs_project(shs_handle *h, int64_t r, const double *V, int64_t ldv, const double *W, int64_t ldw,
+                const int32_t *sel, void *work, size_t work_bytes, double *Ar, double *Er, double *Br, double *Cr,
+                int32_t *rank_def, void *stream);
+
+/*
+ * Structured pseudospectrum (Section 1, the structured epsilon-pseudospectrum
+ * of (A, B, C): the points z with ||C (zI - A)^{-1} B||_2 >= 1/epsilon):
+ *
+ *     norms[j] = ||G_j||_2,   G_j = G(:, j*m : (j+1)*m),  j = 0 .. s-1,
+ *
+ * the largest singular value of each p x m block, e.g. of shs_solve's G at
+ * the points of a grid (the sign of G does not change the norm).  Computed in
+ * FP64 from the Hermitian Gram matrix of the smaller side by Jacobi sweeps;
+ * relative error a few units of rounding.
+ *
+ *   s, p, m   blocks, rows, columns per block (1 <= m <= SHS_MAX_M, p >= 0;
+ *             p == 0 gives zeros and G may then be NULL).
+ *   G, ldg    device, p x (s*m) complex (interleaved), ldg >= max(1, p); read only.
+ *   norms     device, s doubles; NaN for a block holding a NaN or infinity.
+ *   stream    asynchronous on this stream.
+ *
+ * Errors: -1..-6 for bad arguments, SHS_ERR_HIP.  Needs no handle.
+ */
+int shs_transfer_norm2(int64_t s, int64_t p, int64_t m, const double *G, int64_t ldg, double *norms,
+                       void *stream);
+
+/*
  * X_orig = Q X_red: maps ncols reduced-coordinate columns (complex, device,
  * n x ncols, leading dimension ld) to A's coordinates (device, ldo), where
  * X_orig = (A - sigma I)^{-1} B for a solution X_red of the reduced system

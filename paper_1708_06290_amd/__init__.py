@@ -22,10 +22,13 @@ from ._lib import (SHS_ERR_CANCELLED, SHS_ERR_STATE, SHS_MAX_M, SHS_MODE_FP32_RE
                    shs_server_create, shs_server_destroy, shs_server_latency, shs_server_pause, shs_server_poll,
                    shs_server_register, shs_server_stats, shs_server_submit, shs_server_submit_ex,
                    shs_server_wait, shs_set_timing, shs_solve, shs_solve_transposed,
-                   shs_solve_transposed_workspace, shs_solve_workspace)
+                   shs_solve_transposed_vec, shs_solve_transposed_vec_workspace, shs_solve_transposed_workspace,
+                   shs_solve_vec, shs_solve_vec_workspace, shs_solve_workspace, shs_transfer_norm2)
 
 __all__ = ["System", "SolveResult", "library", "shs_reduce", "shs_solve", "shs_solve_workspace",
-           "shs_solve_transposed", "shs_solve_transposed_workspace",
+           "shs_solve_transposed", "shs_solve_transposed_workspace", "shs_transfer_norm2",
+           "shs_solve_vec", "shs_solve_vec_workspace", "shs_solve_transposed_vec",
+           "shs_solve_transposed_vec_workspace",
            "shs_apply_q", "shs_get_reduced", "shs_info", "shs_set_timing", "shs_last_timings",
            "shs_destroy", "ShsError", "Server", "Request", "shs_server_create", "shs_server_register",
            "shs_server_submit", "shs_server_submit_ex", "shs_server_poll", "shs_server_wait", "shs_server_latency",
@@ -132,6 +135,54 @@ class System:
         status = torch.empty(s, dtype=torch.int32, device=self.device)
         shs_solve_transposed(self.handle, shifts, r, Ds, Xs, eta, status, outputs=outputs, stream=stream)
         return SolveResult(Xs.t() if Xs is not None else None, None, eta, status)
+
+    def solve_vec(self, shifts, bhat, outputs=SHS_OUT_X | SHS_OUT_ETA, stream=None):
+        """(H - sigma_j I) x_j = R b_j for an (m, s) complex tensor of directions
+        b_j (Section 3.3); returns a :class:`SolveResult` with X (n, s)."""
+        import torch
+        shifts = torch.as_tensor(shifts, dtype=torch.complex128, device=self.device).reshape(-1).contiguous()
+        s = shifts.numel()
+        bs = torch.as_tensor(bhat, dtype=torch.complex128, device=self.device).reshape(self.m, s).t().contiguous()
+        Xs = torch.empty((s, self.n), dtype=torch.complex128, device=self.device)
+        eta = torch.empty(s, dtype=torch.float64, device=self.device) if outputs & SHS_OUT_ETA else None
+        status = torch.empty(s, dtype=torch.int32, device=self.device)
+        shs_solve_vec(self.handle, shifts, bs, Xs, eta, status, outputs=outputs, stream=stream)
+        return SolveResult(Xs.t(), None, eta, status)
+
+    def solve_transposed_vec(self, shifts, chat, outputs=SHS_OUT_X | SHS_OUT_ETA, stream=None):
+        """(H - sigma_j I)^T w_j = Ct^T c_j for a (p, s) complex tensor of
+        directions c_j (Section 3.3); returns a :class:`SolveResult` with X = W (n, s)."""
+        import torch
+        shifts = torch.as_tensor(shifts, dtype=torch.complex128, device=self.device).reshape(-1).contiguous()
+        s = shifts.numel()
+        cs = (torch.as_tensor(chat, dtype=torch.complex128, device=self.device).reshape(self.p, s).t().contiguous()
+              if self.p > 0 else None)
+        Xs = torch.empty((s, self.n), dtype=torch.complex128, device=self.device) if outputs & SHS_OUT_X else None
+        eta = torch.empty(s, dtype=torch.float64, device=self.device) if outputs & SHS_OUT_ETA else None
+        status = torch.empty(s, dtype=torch.int32, device=self.device)
+        shs_solve_transposed_vec(self.handle, shifts, cs, Xs, eta, status, outputs=outputs, stream=stream)
+        return SolveResult(Xs.t() if Xs is not None else None, None, eta, status)
+
+    def transfer_norm2(self, G, stream=None):
+        """||G_j||_2 per block of a (p, s*m) complex tensor G (e.g. SolveResult.G):
+        the quantity the structured pseudospectrum thresholds (Section 1)."""
+        import torch
+        m = self.m
+        s = G.shape[1] // m
+        Gs = G.t().contiguous() if self.p > 0 else torch.zeros((s * m, 1), dtype=torch.complex128,
+                                                                device=self.device)
+        out = torch.empty(s, dtype=torch.float64, device=self.device)
+        shs_transfer_norm2(Gs[:, : self.p] if self.p > 0 else Gs[:, :0], m, out, stream)
+        return out
+
+    def pseudospectrum(self, points, mode=SHS_MODE_FP32_REFINE, tol=1e-13, max_iter=5, stream=None):
+        """Structured pseudospectrum data on a set of points z: returns
+        (||C (zI - A)^{-1} B||_2 per point, the solve's eta, status).  A point
+        lies in the structured epsilon-pseudospectrum when its value is at
+        least 1/epsilon (Section 1)."""
+        res = self.solve(points, mode=mode, outputs=SHS_OUT_G | SHS_OUT_ETA, tol=tol, max_iter=max_iter,
+                         stream=stream)
+        return self.transfer_norm2(res.G, stream), res.eta, res.status
 
     def apply_q(self, X, stream=None):
         """Q X for an (n, k) complex128 tensor of reduced-coordinate columns."""

@@ -35,7 +35,9 @@ EXPORTED = ("shs_reduce", "shs_solve_workspace", "shs_solve", "shs_apply_q", "sh
             "shs_server_poll", "shs_server_wait", "shs_server_latency", "shs_server_stats",
             "shs_server_destroy", "shs_server_submit_ex", "shs_server_cancel", "shs_server_pause",
             "shs_server_clock", "shs_reduce_check_plan", "shs_solve_transposed",
-            "shs_solve_transposed_workspace")
+            "shs_solve_transposed_workspace", "shs_transfer_norm2", "shs_solve_vec", "shs_solve_vec_workspace",
+            "shs_solve_transposed_vec", "shs_solve_transposed_vec_workspace", "shs_project",
+            "shs_project_workspace")
 
 _lib = None
 
@@ -108,6 +110,18 @@ def _load():
     lib.shs_solve_transposed.argtypes = [vp, i64, dp, i64, dp, i64, ctypes.c_int, vp, ctypes.c_size_t, dp, i64, dp,
                                          vp, vp]
     lib.shs_solve_transposed.restype = ctypes.c_int
+    for nm in ("shs_solve_vec_workspace", "shs_solve_transposed_vec_workspace"):
+        getattr(lib, nm).argtypes = [vp, i64, ctypes.POINTER(ctypes.c_size_t)]
+        getattr(lib, nm).restype = ctypes.c_int
+    for nm in ("shs_solve_vec", "shs_solve_transposed_vec"):
+        getattr(lib, nm).argtypes = [vp, i64, dp, dp, i64, ctypes.c_int, vp, ctypes.c_size_t, dp, i64, dp, vp, vp]
+        getattr(lib, nm).restype = ctypes.c_int
+    lib.shs_project_workspace.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_size_t)]
+    lib.shs_project_workspace.restype = ctypes.c_int
+    lib.shs_project.argtypes = [vp, i64, dp, i64, dp, i64, vp, vp, ctypes.c_size_t, dp, dp, dp, dp, vp, vp]
+    lib.shs_project.restype = ctypes.c_int
+    lib.shs_transfer_norm2.argtypes = [i64, i64, i64, dp, i64, dp, vp]
+    lib.shs_transfer_norm2.restype = ctypes.c_int
     lib.shs_reduce_check_plan.argtypes = [i64, i64, i64, ctypes.POINTER(i64), ctypes.c_char_p, i64]
     lib.shs_reduce_check_plan.restype = ctypes.c_int
     lib.shs_apply_q.argtypes = [vp, i64, dp, i64, dp, i64, vp]
@@ -252,6 +266,61 @@ def shs_solve_transposed(h, shifts, r, D, X, eta, status, outputs=SHS_OUT_X | SH
     rc = lib.shs_solve_transposed(h, s, _ptr(shifts), r, _ptr(D), D.shape[1], outputs, wptr, wbytes, _ptr(X), ldx,
                                   _ptr(eta), _ptr(status), _stream(stream))
     _check("shs_solve_transposed", rc)
+
+
+def shs_solve_vec_workspace(h, s):
+    b = ctypes.c_size_t()
+    _check("shs_solve_vec_workspace", _load().shs_solve_vec_workspace(h, s, ctypes.byref(b)))
+    return b.value
+
+
+def shs_solve_transposed_vec_workspace(h, s):
+    b = ctypes.c_size_t()
+    _check("shs_solve_transposed_vec_workspace", _load().shs_solve_transposed_vec_workspace(h, s, ctypes.byref(b)))
+    return b.value
+
+
+def _vec_call(name, h, shifts, dirs, X, eta, status, outputs, work, stream):
+    s = shifts.numel()
+    wptr, wbytes = (_ptr(work), work.numel() * work.element_size()) if work is not None else (None, 0)
+    ldd = dirs.shape[1] if dirs is not None else 1
+    rc = getattr(_load(), name)(h, s, _ptr(shifts), _ptr(dirs), max(1, ldd), outputs, wptr, wbytes, _ptr(X),
+                                X.shape[1] if X is not None else 1, _ptr(eta), _ptr(status), _stream(stream))
+    _check(name, rc)
+
+
+def shs_solve_vec(h, shifts, bhat, X, eta, status, outputs=SHS_OUT_X | SHS_OUT_ETA, work=None, stream=None):
+    """(H - sigma_j I) x_j = R b_j: ``bhat`` is an (s, m) complex128 tensor
+    (column-major m x s), ``X`` (s, n) (column-major n x s)."""
+    _vec_call("shs_solve_vec", h, shifts, bhat, X, eta, status, outputs, work, stream)
+
+
+def shs_solve_transposed_vec(h, shifts, chat, X, eta, status, outputs=SHS_OUT_X | SHS_OUT_ETA, work=None,
+                             stream=None):
+    """(H - sigma_j I)^T w_j = Ct^T c_j: ``chat`` is an (s, p) complex128
+    tensor (column-major p x s) or None when p = 0, ``X`` (s, n)."""
+    _vec_call("shs_solve_transposed_vec", h, shifts, chat, X, eta, status, outputs, work, stream)
+
+
+def shs_project(h, V, W, sel, Ar, Er, Br, Cr, rank_def, work=None, stream=None):
+    """Projection onto the real bases of V, W ((r, n) complex128 tensors,
+    column-major n x r); ``sel`` (r,) int32; outputs are (r, r), (r, r),
+    (m, r), (r, p) float64 tensors (column-major r x r, r x r, r x m, p x r)
+    and ``rank_def`` (1,) int32."""
+    r = V.shape[0]
+    wptr, wbytes = (_ptr(work), work.numel() * work.element_size()) if work is not None else (None, 0)
+    rc = _load().shs_project(h, r, _ptr(V), V.shape[1], _ptr(W), W.shape[1], _ptr(sel), wptr, wbytes, _ptr(Ar),
+                             _ptr(Er), _ptr(Br), _ptr(Cr), _ptr(rank_def), _stream(stream))
+    _check("shs_project", rc)
+
+
+def shs_transfer_norm2(G, m, norms, stream=None):
+    """||G_j||_2 of every p x m block of G, a (s*m, p) complex128 tensor
+    (column-major p x (s*m)), into ``norms`` ((s,) float64)."""
+    s = G.shape[0] // m
+    p = G.shape[1]
+    _check("shs_transfer_norm2", _load().shs_transfer_norm2(s, p, m, _ptr(G), max(1, p), _ptr(norms),
+                                                            _stream(stream)))
 
 
 def shs_reduce_check_plan(n, m, p):

@@ -76,6 +76,14 @@ hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const in
 // solve can be recorded into a HIP graph and replayed.
 hipError_t zero_fill(void *p, size_t bytes, hipStream_t st);
 
+// C = alpha op(A) op(B) (+ C when accumulate) on the FP64 matrix cores, for
+// other translation units (the GEMM kernels are instantiated once, in the
+// unit of the reduction); part (part_elems doubles, may be null) is the
+// split-K workspace.
+hipError_t dgemm(bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int64_t lda, const double *B,
+                 int64_t ldb, double *C, int64_t ldc, bool accumulate, double *part, size_t part_elems,
+                 hipStream_t st);
+
 // G(:, j*m + c) = Ct X(:, j*m + c) for shifts 0 .. s-1.
 hipError_t g_eval(shs_handle *h, int64_t s, const double *X, int64_t ldx, double *G, int64_t ldg, hipStream_t st);
 

@@ -448,10 +448,34 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     return hipGetLastError();
 }
 
+// Y_j <- [Y_j b_j, 0, ..., 0] for the m x m result Y_j = R_sigma^{-1} R(0:m,0:m)
+// of the sweep (one block per shift; thread i owns row i).
+__global__ __launch_bounds__(64) void vec_y_kernel(int m, double *Y, const double *bhat, int64_t ldb)
+{
+    const int j = blockIdx.x, i = threadIdx.x;
+    if (i >= m) return;
+    double *Yj = Y + (int64_t)j * 2 * m * m;
+    const double *b = bhat + (int64_t)j * ldb * 2;
+    double yr = 0.0, yi = 0.0;
+    for (int c = 0; c < m; ++c) {
+        const double ar = Yj[2 * (c * m + i)], ai = Yj[2 * (c * m + i) + 1];
+        yr = fma(ar, b[2 * c], fma(-ai, b[2 * c + 1], yr));
+        yi = fma(ar, b[2 * c + 1], fma(ai, b[2 * c], yi));
+    }
+    Yj[2 * i] = yr;
+    Yj[2 * i + 1] = yi;
+    for (int c = 1; c < m; ++c) Yj[2 * (c * m + i)] = Yj[2 * (c * m + i) + 1] = 0.0;
+}
+
 // FP64 sweep + Q* pass for the listed shifts into X (dcount: the list's
 // length on the device, count then an upper bound).
+//
+// With per-shift directions bhat (m x count complex, ld ldb; list and count
+// on the device not allowed), each Y_j becomes [Y_j b_j, 0, ..., 0] before
+// the Q* pass, so the shift's first output column is (H - sigma_j I)^{-1} R b_j.
 hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const int *dcount, const double *shifts,
-                      void *work, const Layout &L, double *X, int64_t ldx, int32_t *status, hipStream_t st)
+                      void *work, const Layout &L, double *X, int64_t ldx, int32_t *status, hipStream_t st,
+                      const double *bhat = nullptr, int64_t ldb = 0)
 {
     const int64_t n = h->n, m = h->m;
     Geo g;
@@ -476,6 +500,11 @@ hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const 
     } else {
         PhaseScope ps(h, PH_SWEEP, count, st);
         if (!launch_sweep((int)m, false, sa, st)) return hipErrorInvalidValue;
+    }
+    if (bhat) {
+        if (dlist || dcount) return hipErrorInvalidValue;
+        PhaseScope ps(h, PH_OTHER, count, st);
+        hipLaunchKernelGGL(vec_y_kernel, dim3((unsigned)count), dim3(64), 0, st, (int)m, sa.Y, bhat, ldb);
     }
     QstarArgs<double> qa{};
     qa.n = (int)n;
@@ -751,6 +780,13 @@ hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const in
                        (const unsigned long long *)resmax, (const unsigned long long *)xmax,
                        (const unsigned long long *)opt->emax, eta, status);
     return hipGetLastError();
+}
+
+hipError_t dgemm(bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int64_t lda, const double *B,
+                 int64_t ldb, double *C, int64_t ldc, bool accumulate, double *part, size_t part_elems,
+                 hipStream_t st)
+{
+    return gemm_f64(ta, tb, M, N, K, alpha, A, lda, B, ldb, C, ldc, accumulate, part, part_elems, st);
 }
 
 hipError_t g_eval(shs_handle *h, int64_t s, const double *X, int64_t ldx, double *G, int64_t ldg, hipStream_t st)
@@ -1072,6 +1108,84 @@ size_t reduce_blocked_work(int64_t n, int64_t m, int64_t p)
                              kReducePart);
 }
 
+// ---- per-shift directions (Section 3.3) -----------------------------------
+// The interpolation method solves (A - sigma_j I) x_j = B b_j and
+// (A - sigma_j I)^T w_j = C^T c_j with directions b_j (m) and c_j (p) of
+// their own per shift.  In reduced coordinates the first right-hand side is
+// R b_j, nonzero in its first m rows only, so the structured sweep applies
+// unchanged and only its end differs: y_j = R_sigma(0:m,0:m)^{-1} R(0:m,0:m) b_j
+// and x_j = Q_sigma^*(:, 0:m) y_j.  The second one, Ct^T c_j, is dense and
+// goes through the transposed solve.
+
+// X(:, j) = Xm(:, j m) (the only nonzero column of the shift's Q* output) and,
+// for the backward error, E(:, j) = [R(0:m,0:m) b_j; 0].
+__global__ __launch_bounds__(256) void vec_out_kernel(int n, int m, const double *Xm, double *X, int64_t ldx,
+                                                      const double *Rtop, const double *bhat, int64_t ldb, double *E)
+{
+    const int j = blockIdx.x;
+    const double *src = Xm + (int64_t)j * m * n * 2;
+    const double *b = bhat + (int64_t)j * ldb * 2;
+    for (int i = blockIdx.y * 256 + threadIdx.x; i < n; i += gridDim.y * 256) {
+        if (X) {
+            X[((int64_t)j * ldx + i) * 2] = src[2 * i];
+            X[((int64_t)j * ldx + i) * 2 + 1] = src[2 * i + 1];
+        }
+        if (E) {
+            double er = 0.0, ei = 0.0;
+            for (int c = i; c < m; ++c) {   // R(0:m,0:m) is upper triangular
+                er = fma(Rtop[c * m + i], b[2 * c], er);
+                ei = fma(Rtop[c * m + i], b[2 * c + 1], ei);
+            }
+            E[((int64_t)j * n + i) * 2] = er;
+            E[((int64_t)j * n + i) * 2 + 1] = ei;
+        }
+    }
+}
+
+// Transposed systems with directions: E_j(i, 0) = (Ct^T c_j)(n-1-i) (the
+// order-reversed right-hand side of the sweep of J H^T J), E_j(i, c) = 0 for
+// c >= 1; D_j(i) = (Ct^T c_j)(i) when D is set (for the backward error).
+__global__ __launch_bounds__(256) void tvec_pack_kernel(int n, int m, int p, const double *Ct, int64_t ldct,
+                                                        const double *chat, int64_t ldc, double *E)
+{
+    const int j = blockIdx.x;
+    const double *c = chat + (int64_t)j * ldc * 2;
+    const int64_t total = (int64_t)n * m;
+    for (int64_t idx = (int64_t)blockIdx.y * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.y * 256) {
+        const int col = (int)(idx / n), i = (int)(idx % n);
+        double er = 0.0, ei = 0.0;
+        if (col == 0) {
+            const int r = n - 1 - i;
+            for (int q = 0; q < p; ++q) {
+                const double w = Ct[(int64_t)r * ldct + q];
+                er = fma(w, c[2 * q], er);
+                ei = fma(w, c[2 * q + 1], ei);
+            }
+        }
+        double *e = E + (((int64_t)j * m + col) * n + i) * 2;
+        e[0] = er;
+        e[1] = ei;
+    }
+}
+
+// Workspace of shs_solve_vec: the FP64 solve's layout with a Q* output of m
+// columns per shift, then the right-hand sides [R b_j; 0] and their maxima.
+struct VecLayout {
+    Layout base;
+    size_t e = 0, emax = 0, total = 0;
+};
+
+bool vec_layout(const shs_handle *h, int64_t s, VecLayout *V)
+{
+    if (!layout(h, s, SHS_MODE_FP64, SHS_OUT_G, &V->base)) return false;   // no X output: Q* into the workspace
+    size_t off = V->base.total;
+    auto take = [&](size_t bytes) { size_t o = off; off += al(bytes); return o; };
+    V->e = take(sizeof(double) * 2 * h->n * s);
+    V->emax = take(sizeof(unsigned long long) * s);
+    V->total = off;
+    return true;
+}
+
 }  // namespace
 
 #define RETURN_IF_HIP(expr)                                        \
@@ -1353,22 +1467,12 @@ int shs_solve_transposed_workspace(const shs_handle *h, int64_t s, int64_t r, si
     return 0;
 }
 
-int shs_solve_transposed(shs_handle *h, int64_t s, const double *shifts, int64_t r, const double *D, int64_t ldd,
-                         int outputs, void *work, size_t work_bytes, double *X, int64_t ldx, double *eta,
-                         int32_t *status, void *stream)
+// The transposed solve after argument checks: right-hand sides D (r per
+// shift), or, with chat set (r = 1), Ct^T c_j formed on the device.
+static int transposed_impl(shs_handle *h, int64_t s, const double *shifts, int64_t r, const double *D, int64_t ldd,
+                           const double *chat, int64_t ldc, int outputs, void *work, size_t work_bytes, double *X,
+                           int64_t ldx, double *eta, int32_t *status, void *stream)
 {
-    if (!h) return -1;
-    if (s < 0) return -2;
-    if (s > 0 && !shifts) return -3;
-    if (r < 1) return -4;
-    if (s > 0 && !D) return -5;
-    if (ldd < h->n) return -6;
-    if (!(outputs & SHS_OUT_X) && !(outputs & SHS_OUT_ETA)) return -7;
-    if (outputs & ~(SHS_OUT_X | SHS_OUT_ETA)) return -7;
-    if (s == 0) return 0;
-    if ((outputs & SHS_OUT_X) && (!X || ldx < h->n)) return -10;
-    if ((outputs & SHS_OUT_ETA) && !eta) return -12;
-    if (!status) return -13;
     const int64_t n = h->n, m = h->m;
     TransLayout L;
     if (!trans_layout(h, s, r, &L)) return SHS_ERR_UNSUPPORTED;
@@ -1388,8 +1492,14 @@ int shs_solve_transposed(shs_handle *h, int64_t s, const double *shifts, int64_t
     double *etav = at<double>(work, L.etav);
     const unsigned chunks = std::max<unsigned>(1, std::min<unsigned>(64, cdiv(n * m, 256 * 16)));
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(transposed_pack_kernel, dim3((unsigned)nv, chunks), dim3(256), 0, st, (int)n, (int)m,
-                           (int)r, (int)L.nch, shifts, D, ldd, shv, E);
+        if (chat) {   // r = 1: one item per shift, the shifts as given
+            shv = const_cast<double *>(shifts);
+            hipLaunchKernelGGL(tvec_pack_kernel, dim3((unsigned)nv, chunks), dim3(256), 0, st, (int)n, (int)m,
+                               (int)h->p, (const double *)h->Ct, h->ldct, chat, ldc, E);
+        } else {
+            hipLaunchKernelGGL(transposed_pack_kernel, dim3((unsigned)nv, chunks), dim3(256), 0, st, (int)n,
+                               (int)m, (int)r, (int)L.nch, shifts, D, ldd, shv, E);
+        }
         e = hipGetLastError();
     }
     Geo g;
@@ -1455,6 +1565,120 @@ int shs_solve_transposed(shs_handle *h, int64_t s, const double *shifts, int64_t
                            (outputs & SHS_OUT_ETA) ? (const double *)etav : nullptr, (const int32_t *)stv,
                            (outputs & SHS_OUT_ETA) ? eta : nullptr, status);
         e = hipGetLastError();
+    }
+    if (owned) {
+        hipError_t e2 = hipFreeAsync(work, st);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return (e == hipErrorOutOfMemory) ? SHS_ERR_NOMEM : SHS_ERR_HIP;
+    return 0;
+}
+
+int shs_solve_transposed(shs_handle *h, int64_t s, const double *shifts, int64_t r, const double *D, int64_t ldd,
+                         int outputs, void *work, size_t work_bytes, double *X, int64_t ldx, double *eta,
+                         int32_t *status, void *stream)
+{
+    if (!h) return -1;
+    if (s < 0) return -2;
+    if (s > 0 && !shifts) return -3;
+    if (r < 1) return -4;
+    if (s > 0 && !D) return -5;
+    if (ldd < h->n) return -6;
+    if (!(outputs & SHS_OUT_X) && !(outputs & SHS_OUT_ETA)) return -7;
+    if (outputs & ~(SHS_OUT_X | SHS_OUT_ETA)) return -7;
+    if (s == 0) return 0;
+    if ((outputs & SHS_OUT_X) && (!X || ldx < h->n)) return -10;
+    if ((outputs & SHS_OUT_ETA) && !eta) return -12;
+    if (!status) return -13;
+    return transposed_impl(h, s, shifts, r, D, ldd, nullptr, 0, outputs, work, work_bytes, X, ldx, eta, status,
+                           stream);
+}
+
+int shs_solve_transposed_vec_workspace(const shs_handle *h, int64_t s, size_t *bytes)
+{
+    return shs_solve_transposed_workspace(h, s, 1, bytes);
+}
+
+int shs_solve_transposed_vec(shs_handle *h, int64_t s, const double *shifts, const double *chat, int64_t ldc,
+                             int outputs, void *work, size_t work_bytes, double *X, int64_t ldx, double *eta,
+                             int32_t *status, void *stream)
+{
+    if (!h) return -1;
+    if (s < 0) return -2;
+    if (s > 0 && !shifts) return -3;
+    if (s > 0 && h->p > 0 && !chat) return -4;
+    if (ldc < std::max<int64_t>(1, h->p)) return -5;
+    if (!(outputs & SHS_OUT_X) && !(outputs & SHS_OUT_ETA)) return -6;
+    if (outputs & ~(SHS_OUT_X | SHS_OUT_ETA)) return -6;
+    if (s == 0) return 0;
+    if ((outputs & SHS_OUT_X) && (!X || ldx < h->n)) return -9;
+    if ((outputs & SHS_OUT_ETA) && !eta) return -11;
+    if (!status) return -12;
+    return transposed_impl(h, s, shifts, 1, nullptr, h->n, chat, ldc, outputs, work, work_bytes, X, ldx, eta,
+                           status, stream);
+}
+
+int shs_solve_vec_workspace(const shs_handle *h, int64_t s, size_t *bytes)
+{
+    if (!h) return -1;
+    if (s < 0) return -2;
+    if (!bytes) return -3;
+    VecLayout V;
+    if (!vec_layout(h, s, &V)) return SHS_ERR_UNSUPPORTED;
+    *bytes = V.total;
+    return 0;
+}
+
+int shs_solve_vec(shs_handle *h, int64_t s, const double *shifts, const double *bhat, int64_t ldb, int outputs,
+                  void *work, size_t work_bytes, double *X, int64_t ldx, double *eta, int32_t *status, void *stream)
+{
+    if (!h) return -1;
+    if (s < 0 || s > INT32_MAX / 64) return -2;
+    if (s > 0 && !shifts) return -3;
+    if (s > 0 && !bhat) return -4;
+    if (ldb < h->m) return -5;
+    if (!(outputs & SHS_OUT_X) && !(outputs & SHS_OUT_ETA)) return -6;
+    if (outputs & ~(SHS_OUT_X | SHS_OUT_ETA)) return -6;
+    if (s == 0) return 0;
+    if (!X || ldx < h->n) return -9;   // X is also the residual's input
+    if ((outputs & SHS_OUT_ETA) && !eta) return -11;
+    if (!status) return -12;
+    const int64_t n = h->n, m = h->m;
+    VecLayout V;
+    if (!vec_layout(h, s, &V)) return SHS_ERR_UNSUPPORTED;
+    hipStream_t st = (hipStream_t)stream;
+    if (h->timing) {
+        h->marks.clear();
+        h->last_mixed = false;
+        h->tile_flops = h->update_flops = 0.0;
+    }
+    bool owned = false;
+    if (work) {
+        if (work_bytes < V.total) return -8;
+    } else {
+        RETURN_IF_HIP(hipMallocAsync(&work, V.total, st));
+        owned = true;
+    }
+    const Layout &L = V.base;
+    double *Xm = at<double>(work, L.x);   // Q* output, m columns per shift (the first one nonzero)
+    hipError_t e = solve_fp64(h, s, nullptr, nullptr, shifts, work, L, Xm, n, status, st, bhat, ldb);
+    const bool want_eta = outputs & SHS_OUT_ETA;
+    double *E = want_eta ? at<double>(work, V.e) : nullptr;
+    if (e == hipSuccess) {
+        PhaseScope ps(h, PH_OTHER, s, st);
+        hipLaunchKernelGGL(vec_out_kernel, dim3((unsigned)s, std::max<unsigned>(1, std::min<unsigned>(16, cdiv(n, 256)))),
+                           dim3(256), 0, st, (int)n, (int)m, (const double *)Xm, X, ldx, (const double *)h->Rtop,
+                           bhat, ldb, E);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && want_eta) {
+        CertifyOpts co;
+        co.nc = 1;
+        co.E = E;
+        co.lde = n;
+        co.emax = at<unsigned long long>(work, V.emax);
+        e = certify(h, s, nullptr, nullptr, shifts, X, ldx, nullptr, at<unsigned long long>(work, L.resmax),
+                    at<unsigned long long>(work, L.xmax), eta, status, s, at<double>(work, L.xt), st, &co);
     }
     if (owned) {
         hipError_t e2 = hipFreeAsync(work, st);

@@ -35,6 +35,7 @@ from ._lib import SHS_OUT_ETA, SHS_OUT_X, shs_project
 @dataclasses.dataclass
 class IrkaResult:
     points: list            # ordered points of every iteration (the start first)
+    directions: list        # (b, c) directions that went with each entry of points (m x r, p x r)
     Ar: np.ndarray          # last projection: r x r, r x r, r x m, p x r
     Er: np.ndarray
     Br: np.ndarray
@@ -93,6 +94,7 @@ def irka(system, points, bdir, cdir, iters: int = 30, stream=None) -> IrkaResult
     P, Bd, Cd, sel = _arrange(points, bdir, cdir, 0.0)
     r = P.size
     history = [P]
+    dirs = [(Bd, Cd)]
     out = None
     max_eta = 0.0
     t_solve = t_proj = t_host = 0.0
@@ -124,10 +126,11 @@ def irka(system, points, bdir, cdir, iters: int = 30, stream=None) -> IrkaResult
             cn = np.zeros((0, r), dtype=np.complex128)
         P, Bd, Cd, sel = _arrange(pts, bn, cn, 1e-14)
         history.append(P)
+        dirs.append((Bd, Cd))
         t3 = time.perf_counter()
         t_solve += t1 - t0
         t_proj += t2 - t1
         t_host += t3 - t2
     if out is None:
         out = (np.zeros((r, r)), np.zeros((r, r)), np.zeros((r, m)), np.zeros((p, r)))
-    return IrkaResult(history, *out, max_eta, t_solve, t_proj, t_host)
+    return IrkaResult(history, dirs, *out, max_eta, t_solve, t_proj, t_host)

@@ -59,6 +59,10 @@ extern "C" {
 #define SHS_ERR_TIMEOUT      6  /* wait timed out (serving) */
 #define SHS_ERR_CANCELLED    7  /* the request was cancelled (serving) */
 #define SHS_ERR_STATE        8  /* the request is not in a state that allows the call (serving) */
+#define SHS_ERR_SCRATCH      9  /* the solve needs more than shs_solve_noalloc's static scratch */
+
+/* bytes of the static per-GPU scratch of shs_solve_noalloc */
+#define SHS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
 
 /* per-shift status codes written by shs_solve */
 #define SHS_STATUS_OK             0
@@ -181,6 +185,30 @@ int shs_solve(shs_handle *h, int64_t s, const double *shifts,
               void *work, size_t work_bytes,
               double *X, int64_t ldx, double *G, int64_t ldg,
               double *eta, int32_t *status, void *stream);
+
+/*
+ * shs_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, arguments and results as shs_solve, with its workspace taken
+ * from a static per-GPU array of SHS_NOALLOC_SCRATCH_BYTES (128 MiB) inside
+ * the library instead of `work`.  The call makes no hipMalloc, hipFree or
+ * other allocation; the array exists on every GPU the library is used on
+ * until the process ends (its address is looked up on the first call on a
+ * device).
+ *
+ *   Requests whose shs_solve_workspace bytes exceed SHS_NOALLOC_SCRATCH_BYTES
+ *   fail with SHS_ERR_SCRATCH before any work is queued.  The handle's device
+ *   must be current (else SHS_ERR_STATE), and phase timing must be off
+ *   (shs_set_timing(h, 0), else SHS_ERR_STATE).
+ *
+ *   All calls on one GPU share that GPU's array: calls whose work can
+ *   overlap on the device (different streams, or threads) race and must be
+ *   serialised by the caller, e.g. by issuing them on one stream.  The array
+ *   keeps the last call's contents; every call clears what it needs cleared.
+ */
+int shs_solve_noalloc(shs_handle *h, int64_t s, const double *shifts, int mode, int outputs, double tol,
+                      int max_iter, double *X, int64_t ldx, double *G, int64_t ldg, double *eta,
+                      int32_t *status, void *stream);
 
 /*
  * Transposed systems with unstructured right-hand sides (Section 3.3, the

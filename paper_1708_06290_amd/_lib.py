@@ -28,6 +28,8 @@ SHS_MAX_M = 16
 SHS_REQ_QUEUED, SHS_REQ_RUNNING, SHS_REQ_DONE, SHS_REQ_FAILED, SHS_REQ_CANCELLED = range(5)
 SHS_ERR_CANCELLED = 7
 SHS_ERR_STATE = 8
+SHS_ERR_SCRATCH = 9
+SHS_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 EXPORTED = ("shs_reduce", "shs_solve_workspace", "shs_solve", "shs_apply_q", "shs_get_reduced",
             "shs_info", "shs_set_timing", "shs_last_timings", "shs_destroy", "shs_strerror",
@@ -116,6 +118,9 @@ def _load():
     for nm in ("shs_solve_vec", "shs_solve_transposed_vec"):
         getattr(lib, nm).argtypes = [vp, i64, dp, dp, i64, ctypes.c_int, vp, ctypes.c_size_t, dp, i64, dp, vp, vp]
         getattr(lib, nm).restype = ctypes.c_int
+    lib.shs_solve_noalloc.argtypes = [vp, i64, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                      dp, i64, dp, i64, dp, vp, vp]
+    lib.shs_solve_noalloc.restype = ctypes.c_int
     lib.shs_project_workspace.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_size_t)]
     lib.shs_project_workspace.restype = ctypes.c_int
     lib.shs_project.argtypes = [vp, i64, dp, i64, dp, i64, vp, vp, ctypes.c_size_t, dp, dp, dp, dp, vp, vp]
@@ -248,6 +253,17 @@ def shs_solve(h, shifts, X, G, eta, status, mode=SHS_MODE_FP64, outputs=SHS_OUT_
     rc = lib.shs_solve(h, s, _ptr(shifts), mode, outputs, tol, max_iter, wptr, wbytes,
                        _ptr(X), ldx, _ptr(G), ldg, _ptr(eta), _ptr(status), _stream(stream))
     _check("shs_solve", rc)
+
+
+def shs_solve_noalloc(h, shifts, X, G, eta, status, mode=SHS_MODE_FP64, outputs=SHS_OUT_X | SHS_OUT_G,
+                      tol=1e-13, max_iter=5, stream=None):
+    """As :func:`shs_solve` with the library's static scratch as workspace
+    (no device allocation); returns the library's code (0 or an error)."""
+    s = shifts.numel()
+    ldx = X.shape[1] if X is not None else 1
+    ldg = G.shape[1] if G is not None else 1
+    return _load().shs_solve_noalloc(h, s, _ptr(shifts), mode, outputs, tol, max_iter, _ptr(X), ldx, _ptr(G), ldg,
+                                     _ptr(eta), _ptr(status), _stream(stream))
 
 
 def shs_solve_transposed_workspace(h, s, r):

@@ -1188,6 +1188,39 @@ bool vec_layout(const shs_handle *h, int64_t s, VecLayout *V)
 
 }  // namespace
 
+// ---- scratch of shs_solve_noalloc ------------------------------------------
+// One array per GPU the library runs on (the code object holds it; the GPU
+// keeps it until the process ends).  Host code must not use the name
+// `scratch` as an address: it is a host-side stand-in.  Its device address
+// is taken once per device with hipGetSymbolAddress and kept in
+// g_scratch_ptr, which is what kernels and copies receive.
+constexpr size_t kNoAllocBytes = SHS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current.
+hipError_t noalloc_scratch(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || ((uintptr_t)p & 255)) return hipErrorInvalidValue;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
 #define RETURN_IF_HIP(expr)                                        \
     do {                                                           \
         hipError_t e_ = (expr);                                    \
@@ -1214,6 +1247,7 @@ const char *shs_strerror(int code)
     case SHS_ERR_TIMEOUT: return "timed out";
     case SHS_ERR_CANCELLED: return "cancelled";
     case SHS_ERR_STATE: return "request already finished or not finished";
+    case SHS_ERR_SCRATCH: return "the solve needs more than the static scratch of shs_solve_noalloc";
     default: return "unknown error";
     }
 }
@@ -1396,6 +1430,32 @@ int shs_solve_workspace(const shs_handle *h, int64_t s, int mode, int outputs, s
     if (!layout(h, s, mode, outputs, &L)) return SHS_ERR_UNSUPPORTED;
     *bytes = L.total;
     return 0;
+}
+
+int shs_solve_noalloc(shs_handle *h, int64_t s, const double *shifts, int mode, int outputs, double tol,
+                      int max_iter, double *X, int64_t ldx, double *G, int64_t ldg, double *eta, int32_t *status,
+                      void *stream)
+{
+    if (!h) return -1;
+    if (s < 0 || s > INT32_MAX / 64) return -2;
+    if (mode != SHS_MODE_FP64 && mode != SHS_MODE_FP32_REFINE) return -4;
+    if (!(outputs & (SHS_OUT_X | SHS_OUT_G))) return -5;
+    if (s == 0) return 0;
+    if (h->timing) return SHS_ERR_STATE;   // phase timing creates events and grows host vectors
+    Layout L;
+    if (!layout(h, s, mode, outputs, &L)) return SHS_ERR_UNSUPPORTED;
+    if (L.total > kNoAllocBytes) return SHS_ERR_SCRATCH;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return SHS_ERR_HIP;
+    if (dev != h->device) return SHS_ERR_STATE;
+    void *ptr = nullptr;
+    const hipError_t e = noalloc_scratch(dev, &ptr);
+    if (e != hipSuccess) return SHS_ERR_HIP;
+    // every buffer the solve reads before writing it is cleared by its own
+    // kernels (the same holds for a fresh allocation), so what the previous
+    // call left in the array does not matter
+    return shs_solve(h, s, shifts, mode, outputs, tol, max_iter, ptr, kNoAllocBytes, X, ldx, G, ldg, eta, status,
+                     stream);
 }
 
 int shs_solve(shs_handle *h, int64_t s, const double *shifts, int mode, int outputs, double tol, int max_iter,

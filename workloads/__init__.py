@@ -171,3 +171,31 @@ def modal_system(n: int, m: int, p: int, seed: int, k: int = 4) -> ModalSystem:
     B = rng.standard_normal((n, m))
     C = rng.standard_normal((p, n))
     return ModalSystem(np.asfortranarray(A), np.asfortranarray(B), np.asfortranarray(C), V, blocks)
+
+
+# The interpolation method's workload (Section 4.5: random systems, n up to
+# 15000, m = p in {1, 10, 32}, reduced order r = 100, 30 iterations; m = 32
+# is beyond this library's m <= 16).
+IRKA_N, IRKA_M, IRKA_R, IRKA_ITERS = 15000, 10, 100, 30
+IRKA_SEED = SEED_BASE + 6
+
+
+def irka_start(m: int, p: int, r: int, seed: int):
+    """Start of the interpolation method: r/2 conjugate pairs on the circle
+    of radius 1 about 1.5 (the mirror image of the boundary of the spectral
+    disc of A = N(0, 1/n) - 1.5 I), angles (k + 1/2) pi / (r/2) in the upper
+    half plane, and N(0, 1) complex directions b (m) and c (p), conjugate
+    within each pair.  Returns (points r, b m x r, c p x r)."""
+    rng = np.random.default_rng(seed)
+    half = r // 2
+    th = (np.arange(half) + 0.5) * np.pi / half
+    up = 1.5 + np.exp(1j * th)
+    pts = np.empty(2 * half, dtype=np.complex128)
+    pts[0::2], pts[1::2] = up, np.conj(up)
+    bd = rng.standard_normal((m, half)) + 1j * rng.standard_normal((m, half))
+    cd = rng.standard_normal((p, half)) + 1j * rng.standard_normal((p, half))
+    B = np.empty((m, 2 * half), dtype=np.complex128)
+    Cd = np.empty((p, 2 * half), dtype=np.complex128)
+    B[:, 0::2], B[:, 1::2] = bd, np.conj(bd)
+    Cd[:, 0::2], Cd[:, 1::2] = cd, np.conj(cd)
+    return pts, B, Cd

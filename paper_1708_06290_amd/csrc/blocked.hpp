@@ -56,6 +56,7 @@
 #pragma once
 
 #include "sweep.hpp"
+#include "kernels.hpp"
 
 namespace shs {
 
@@ -64,45 +65,66 @@ __host__ __device__ constexpr int blk_width(int m)
     return m <= 1 ? 2 : (m <= 2 ? 4 : (m <= 4 ? 8 : (m <= 8 ? 16 : 32)));
 }
 
-struct BlkTriArgs {
+// Real columns per shift of the carried-column array: 2m for the carried
+// columns z, and with a dense right-hand side 2m more for e (its m columns'
+// real parts, then imaginary parts), rounded up to a power of two.
+__host__ __device__ constexpr int blk_cols(int m, bool dense) { return blk_width(dense ? 2 * m : m); }
+
+template <typename T>
+struct BlkTriArgsT {
     int n;
     int count;                 // work items (= launched workgroups)
     int t, ntiles;             // this row tile, number of row tiles
-    const double *H;
+    const T *H;
     int64_t ldh;
     const double *shifts;      // interleaved complex, by shift id
     const int32_t *list;       // work item -> shift id (nullptr = identity)
     const double *Rtop;        // m x m upper triangle of R (ld m)
-    double *refl;              // per shift id reflector store
+    T *refl;                   // per shift id reflector store
     int64_t refl_stride;
-    double *Y;                 // per shift id m x m complex
+    T *Y;                      // per shift id: m x m complex, or n x m with a dense right-hand side
     int64_t y_stride;
     int32_t *status;           // per shift id
-    const double *Z;           // carried columns (see above), ld ldz
+    const T *Z;                // carried columns (see above), ld ldz
     int64_t ldz;
-    double *Bm;                // M1 (and for the bottom tile M2) rows, row-major: row k at Bm + k ldb
+    T *Bm;                     // M1 (and for the bottom tile M2) rows, row-major: row k at Bm + k ldb
     int64_t ldb;               // row stride of Bm (columns of Z, a multiple of 128)
-    double *M2;                // per work item W x W real (row-major), non-bottom tiles
-    const double *M2p;         // per work item W x W: composite M2 of the group so far (k >= 2)
-    double *M2q;               // per work item W x W: composite M2 including this tile
+    T *M2;                     // per work item W x W real (row-major): written by a dense bottom tile
+    const T *M2p;              // per work item W x W: composite M2 of the group so far (k >= 2)
+    T *M2q;                    // per work item W x W: composite M2 including this tile
     int gk;                    // 0: bottom tile; k = 1 .. D: k-th tile of a group
     int D;                     // tiles per group; Bm holds D TT + m rows
     const int *dcount;         // if set, the number of work items is read here (count is an upper bound)
 };
+using BlkTriArgs = BlkTriArgsT<double>;
 
 // Block-transform destinations (n_b = TT rows of M1 per tile):
 //   bottom        Bm rows 0 .. n_b+m-1 (M1 and M2, K = n_b + m)
 //   k-th of group M1 -> Bm rows (D-k) TT .. (D-k+1) TT - 1; rows below it,
 //                 up to D TT - 1, <- themselves times M2; M2q <- M2p M2
-template <int M>
-__global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
+//
+// With a dense right-hand side (DENSE: e_i, m complex values per row, in Z
+// after the carried columns) the rows above the tile also need
+// e_i -= sum_k R_sigma(i, k) y_k over the tile's steps k.  R_sigma(i, k) is
+// the column that leaves the window at step k, a linear function of the
+// row's window before the tile, so the sum is [H(i, fresh) z_i] N_blk with
+// N_blk = sum_k P_{hi-1} ... P_k e_k y_k (e_k the unit vector of window
+// column k), which the recursion v <- P_k (v + e_k y_k), k = lo .. hi-1,
+// forms next to M_blk: the same sliding window, with y_k entering where M_blk
+// lets a zero row in.  The GEMM operand of a shift becomes [M1 | -N1] and
+// the carried matrix [[M2, -N2], [0, I]], which maps [z e] to
+// [z M2, e - z N2]; the bottom tile folds M2 and -N2 into K and carries e
+// through the identity.
+template <typename T, int M, bool DENSE>
+__global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
 {
-    using T = double;
-    using Sh = SweepShape<T, M, false>;
-    constexpr int R = Sh::R, TT = Sh::TT, S = Sh::S, NP = Sh::NP;
-    constexpr int W = blk_width(M);
+    using Sh = SweepShape<T, M, DENSE>;
+    constexpr int R = Sh::R, TT = Sh::TT, S = Sh::S, NP = Sh::NP, EM = Sh::EM;
+    constexpr int W = blk_cols(M, DENSE);
+    constexpr int AW = DENSE ? 4 * M : 2 * M;   // active real columns per shift
+    constexpr int NL = DENSE ? 2 * M : M;       // lanes forming the block transform
     __shared__ T lds_rs[2 * M * M];
-    __shared__ T lds_m2[W * W];   // M2_b of a second tile, real form
+    __shared__ T lds_m2[W * W];   // the carried matrix of this tile, real form
     const int item = blockIdx.x;
     if (item >= (a.dcount ? *a.dcount : a.count)) return;
     const int sid = a.list ? a.list[item] : item;
@@ -110,21 +132,21 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
     const int n = a.n, t = a.t;
     const int lo = t * TT, hi = min(n, lo + TT);
     const bool bottom = t == a.ntiles - 1;
-    const T sgr = a.shifts[2 * sid], sgi = a.shifts[2 * sid + 1];
+    const T sgr = (T)a.shifts[2 * sid], sgi = (T)a.shifts[2 * sid + 1];
     T *rf = a.refl + (int64_t)sid * a.refl_stride;
     T *Y = a.Y + (int64_t)sid * a.y_stride;
     const int64_t tstride = refl_tile_stride<T>(TT, S);
-    const double *H = a.H;
+    const T *H = a.H;
     const int64_t ldh = a.ldh;
 
     // ---- window at step hi-1: slot p holds position j = (p - (hi-1)) mod (m+1),
     // column hi-1-m+j.  Position 0 is the fresh column hi-1-m (from H); the
     // others are the carried columns hi-m .. hi-1 (from Z, or from H for the
     // bottom tile).  Rows past n only exist in the bottom tile.
-    T wr[R][NP], wi[R][NP], er[R][1], ei[R][1];
+    T wr[R][NP], wi[R][NP], er[R][EM], ei[R][EM];
     {
         const int q0 = (hi - 1) % NP;
-        const double *Zi = a.Z + (int64_t)item * W * a.ldz;
+        const T *Zi = a.Z + (int64_t)item * W * a.ldz;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int j = (p - q0 + NP) % NP;
@@ -139,8 +161,8 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
                     wi[r][p] = dg ? -sgi : T(0);
                 }
             } else {
-                const double *zr = Zi + (int64_t)(j - 1) * a.ldz;
-                const double *zi = Zi + (int64_t)(M + j - 1) * a.ldz;
+                const T *zr = Zi + (int64_t)(j - 1) * a.ldz;
+                const T *zi = Zi + (int64_t)(M + j - 1) * a.ldz;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int i = lo + r * kWave + lane;
@@ -149,20 +171,36 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
                 }
             }
         }
+        if constexpr (DENSE) {
+            // the tile's rows of the right-hand side, after every tile below
 #pragma unroll
-        for (int r = 0; r < R; ++r) { er[r][0] = T(0); ei[r][0] = T(0); }
+            for (int c = 0; c < M; ++c) {
+                const T *pr = Zi + (int64_t)(2 * M + c) * a.ldz;
+                const T *pi = Zi + (int64_t)(3 * M + c) * a.ldz;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = lo + r * kWave + lane;
+                    er[r][c] = i < n ? pr[i] : T(0);
+                    ei[r][c] = i < n ? pi[i] : T(0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) { er[r][0] = T(0); ei[r][0] = T(0); }
+        }
     }
 
     bool singular = false, nonfinite = false;
-    tri_phase<T, M, false, true>(n, lo, hi, lane, H, ldh, sgr, sgi, rf, tstride, Y, lds_rs, wr, wi, er, ei, singular,
-                           nonfinite);
+    tri_phase<T, M, DENSE, true>(n, lo, hi, lane, H, ldh, sgr, sgi, rf, tstride, Y, lds_rs, wr, wi, er, ei, singular,
+                                 nonfinite);
     // the tile's reflector stores complete before they are read back below
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 
     if (t == 0) {
         // earlier tiles recorded a singular step in the status word
         const bool before = !bottom && a.status[sid] == 1;
-        finish_shift<T, M, false>(n, lane, a.Rtop, Y, lds_rs, a.status + sid, singular || before, nonfinite);
+        if constexpr (DENSE) nonfinite = __any(nonfinite);
+        finish_shift<T, M, DENSE>(n, lane, a.Rtop, Y, lds_rs, a.status + sid, singular || before, nonfinite);
         return;
     }
     if (lane == 0 && (bottom || singular)) a.status[sid] = singular ? 1 : 0;
@@ -171,10 +209,11 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
     // P_k acts on rows k-lo .. k-lo+m of M_blk.  Applied from P_lo upwards, row
     // p is final once P_{lo+p} is done, so each lane keeps a window of m+1
     // rows (row p in slot p mod (m+1)), emits the finished row and lets the
-    // next (zero) row in.  The tile's reflectors come back through LDS in
-    // chunks of CS steps that the whole wave loads (coalesced, the next chunk
-    // in flight while the current one is used), so the serial chain never
-    // waits on memory.
+    // next (zero) row in.  With a dense right-hand side, lane m + c forms
+    // column c of N_blk the same way, y_k(c) entering at row k-lo+m before
+    // P_k.  The tile's reflectors come back through LDS in chunks of CS steps
+    // that the whole wave loads (coalesced, the next chunk in flight while
+    // the current one is used), so the serial chain never waits on memory.
     {
         // steps per chunk: whole phase groups, about 12 elements per lane
         constexpr int CS = NP * ((12 * kWave / S) / NP > 0 ? (12 * kWave / S) / NP : 1);
@@ -182,17 +221,22 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
         constexpr int PL = (CE + kWave - 1) / kWave;
         __shared__ T lds_ch[CE];
         T pre[PL];
-        const int c = lane < M ? lane : 0;
+        const bool isn = DENSE && lane >= M && lane < 2 * M;   // an N_blk column
+        const int c = lane < NL ? (isn ? lane - M : lane) : 0;
         const int nb = hi - lo;
         const int K = bottom ? nb + M : nb;
         const int boff = a.gk >= 1 ? (a.D - a.gk) * TT : 0;
-        // row p of the block transform is row boff + p of Bm; this shift's
-        // real and imaginary parts are its columns item W + c and item W + m + c
-        double *bcr = a.Bm + (int64_t)boff * a.ldb + item * W + c;
-        double *bci = bcr + M;
-        // M2 is assembled in LDS and used right here (the bottom tile has
-        // none: its K covers it)
-        for (int e = lane; e < W * W; e += kWave) lds_m2[e] = T(0);
+        // row p of the block transform is row boff + p of Bm; this column's
+        // real and imaginary parts are the shift's columns cre and cre + m
+        const int cre = isn ? 2 * M + c : c;
+        T *bcr = a.Bm + (int64_t)boff * a.ldb + item * W + cre;
+        T *bci = bcr + M;
+        // the carried matrix is assembled in LDS: z rows times M2 and -N2, the
+        // identity for e
+        for (int e = lane; e < W * W; e += kWave) {
+            const int rr = e / W, cc = e % W;
+            lds_m2[e] = (DENSE && rr == cc && rr >= 2 * M && rr < 4 * M) ? T(1) : T(0);
+        }
         // slots past hi - 1 are loaded from a clamped address and never used
         auto fetch = [&](int cb) {
 #pragma unroll
@@ -207,23 +251,26 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
         // a shift with a non-finite sigma gets a zero transform: its own
         // result is flagged by its status, and its Z columns stay finite
         const bool bad = !isfinite(sgr) || !isfinite(sgi);
+        const T sgn = isn ? T(-1) : T(1);   // the operand holds -N_blk
         auto emit = [&](int p, T xr, T xi) {
             if (bad) xr = xi = T(0);
+            xr *= sgn;
+            xi *= sgn;
             if (p < K) {
                 bcr[(int64_t)p * a.ldb] = xr;
                 bci[(int64_t)p * a.ldb] = xi;
             } else {
-                // real form of z M2: [zr zi] [[Re, Im], [-Im, Re]]
+                // real form of z times the m x m block: [zr zi] [[Re, Im], [-Im, Re]]
                 const int cp = p - nb;
-                lds_m2[cp * W + c] = xr;
-                lds_m2[cp * W + M + c] = xi;
-                lds_m2[(M + cp) * W + c] = -xi;
-                lds_m2[(M + cp) * W + M + c] = xr;
+                lds_m2[cp * W + cre] = xr;
+                lds_m2[cp * W + M + cre] = xi;
+                lds_m2[(M + cp) * W + cre] = -xi;
+                lds_m2[(M + cp) * W + M + cre] = xr;
             }
         };
         T ur[NP], ui[NP];
 #pragma unroll
-        for (int p = 0; p < NP; ++p) { ur[p] = p == c ? T(1) : T(0); ui[p] = T(0); }
+        for (int p = 0; p < NP; ++p) { ur[p] = (!isn && p == c) ? T(1) : T(0); ui[p] = T(0); }
         fetch(lo);
         for (int cb = lo; cb < hi; cb += CS) {
             // one wave per workgroup: its LDS operations complete in order,
@@ -234,7 +281,7 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
                 if (idx < CE) lds_ch[idx] = pre[e];
             }
             if (cb + CS < hi) fetch(cb + CS);
-            if (lane < M) {
+            if (lane < NL) {
             const int ce = min(hi, cb + CS);
             for (int kb = cb; kb < ce; kb += NP) {
             static_for<NP>([&](auto sc) {
@@ -246,6 +293,13 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
                     T vr[M], vi[M];
 #pragma unroll
                     for (int j = 0; j < M; ++j) { vr[j] = pv[2 + 2 * j]; vi[j] = pv[3 + 2 * j]; }
+                    if constexpr (DENSE) {
+                        // y_k(c) enters at window position m (row k-lo+m)
+                        if (isn) {
+                            ur[(st + M) % NP] += pv[2 + 2 * M + 2 * c];
+                            ui[(st + M) % NP] += pv[3 + 2 * M + 2 * c];
+                        }
+                    }
                     // s = v^* u over positions j = 0 .. m (v_m = 1); position j in slot (st + j) mod (m+1)
                     T sr = ur[(st + M) % NP], si = ui[(st + M) % NP];
 #pragma unroll
@@ -272,7 +326,7 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
             }
         }
         // rows nb .. nb+m-1 are still in the window (row nb+m is the zero row)
-        if (lane < M) {
+        if (lane < NL) {
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
                 const int p = nb + ((q - nb % NP) + NP) % NP;
@@ -280,33 +334,38 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
             }
         }
         // one wave: its LDS writes above are complete before these reads
+        if (DENSE && bottom) {
+            // the bottom tile's operand covers z through K; e goes through
+            T *pm = a.M2 + (int64_t)item * W * W;
+            for (int e = lane; e < W * W; e += kWave) pm[e] = lds_m2[e];
+        }
         if (a.gk == 1) {
-            double *pm = a.M2q + (int64_t)item * W * W;
+            T *pm = a.M2q + (int64_t)item * W * W;
             for (int e = lane; e < W * W; e += kWave) pm[e] = lds_m2[e];
         }
         if (a.gk >= 2) {
             // the older composite rows: B <- B M2 (real form)
             const int r1 = (a.D - a.gk + 1) * TT, nrows = (a.gk - 1) * TT;
-            double *bb = a.Bm + (int64_t)r1 * a.ldb + item * W;
+            T *bb = a.Bm + (int64_t)r1 * a.ldb + item * W;
             // each lane one row at a time: the whole row first (its loads in
-            // flight together; up to m = 8 the next row's are issued before
-            // this one is multiplied, beyond that the registers are short),
-            // then the product with M2 from LDS; the opaque offset keeps the
-            // compiler from hoisting all (2m)^2 LDS reads out of the row loop
-            // into registers
-            constexpr bool PF = M <= 8;
-            T o[2 * M];
+            // flight together; up to 16 active columns the next row's are
+            // issued before this one is multiplied, beyond that the registers
+            // are short), then the product with M2 from LDS; the opaque
+            // offset keeps the compiler from hoisting all the LDS reads out
+            // of the row loop into registers
+            constexpr bool PF = AW <= 16;
+            T o[AW];
             if (PF && lane < nrows) {
 #pragma unroll
-                for (int q = 0; q < 2 * M; ++q) o[q] = bb[(int64_t)lane * a.ldb + q];
+                for (int q = 0; q < AW; ++q) o[q] = bb[(int64_t)lane * a.ldb + q];
             }
 #pragma unroll 1
             for (int p = lane; p < nrows; p += kWave) {
-                double *row = bb + (int64_t)p * a.ldb;
-                T on[2 * M], nw[2 * M];
+                T *row = bb + (int64_t)p * a.ldb;
+                T on[AW], nw[AW];
                 const int pn = p + kWave < nrows ? p + kWave : p;
 #pragma unroll
-                for (int q = 0; q < 2 * M; ++q) {
+                for (int q = 0; q < AW; ++q) {
                     if constexpr (PF) on[q] = bb[(int64_t)pn * a.ldb + q];
                     else o[q] = row[q];
                     nw[q] = T(0);
@@ -314,27 +373,27 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgs a)
                 int z = 0;
                 asm volatile("" : "+v"(z));
 #pragma unroll
-                for (int q = 0; q < 2 * M; ++q)
+                for (int q = 0; q < AW; ++q)
 #pragma unroll
-                    for (int qq = 0; qq < 2 * M; ++qq) nw[qq] = fma(o[q], lds_m2[z + q * W + qq], nw[qq]);
+                    for (int qq = 0; qq < AW; ++qq) nw[qq] = fma(o[q], lds_m2[z + q * W + qq], nw[qq]);
 #pragma unroll
-                for (int q = 0; q < 2 * M; ++q) {
+                for (int q = 0; q < AW; ++q) {
                     row[q] = nw[q];
                     if constexpr (PF) o[q] = on[q];
                 }
             }
             // M2q <- M2p M2
-            const double *pa = a.M2p + (int64_t)item * W * W;
-            double *pm = a.M2q + (int64_t)item * W * W;
-            for (int e = lane; e < 4 * M * M; e += kWave) {
-                const int k = e / (2 * M), qq = e % (2 * M);
+            const T *pa = a.M2p + (int64_t)item * W * W;
+            T *pm = a.M2q + (int64_t)item * W * W;
+            for (int e = lane; e < AW * AW; e += kWave) {
+                const int k = e / AW, qq = e % AW;
                 // row k of M2p first (its loads in flight together)
-                T r[2 * M];
+                T r[AW];
 #pragma unroll
-                for (int q = 0; q < 2 * M; ++q) r[q] = pa[k * W + q];
+                for (int q = 0; q < AW; ++q) r[q] = pa[k * W + q];
                 T acc = T(0);
 #pragma unroll
-                for (int q = 0; q < 2 * M; ++q) acc = fma(r[q], lds_m2[q * W + qq], acc);
+                for (int q = 0; q < AW; ++q) acc = fma(r[q], lds_m2[q * W + qq], acc);
                 pm[k * W + qq] = acc;
             }
         }
@@ -347,6 +406,7 @@ struct ZupdArgs {
     int c0;                    // first column of H in the block (lo - m)
     int K;                     // rows of M_blk multiplying H (n_b + m bottom, k n_b otherwise)
     int m;
+    int nr;                    // right-hand-side columns carried after z (dense right-hand side: m), else 0
     int n;                     // order of H: columns past n-1 are never read
     int ncols;                 // columns of Z (W per work item, a multiple of 128)
     int count;                 // work items
@@ -531,13 +591,16 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgs a)
                     const int w = j / W, q = j % W;
                     const int sid = w < count ? (a.list ? a.list[w] : w) : 0;
                     const double sr = a.shifts[2 * sid], si = a.shifts[2 * sid + 1];
-                    // a non-finite sigma has a zero transform and keeps Z zero
-                    if (w < count && q < 2 * m && isfinite(sr) && isfinite(si)) {
-                        const int c = q < m ? q : q - m;
+                    // a non-finite sigma has a zero transform and keeps Z zero.
+                    // Column pairs (re, im): (c, m + c) of the carried columns,
+                    // (2m + c, 3m + c) of a dense right-hand side.
+                    const int base = q < 2 * m ? 0 : 2 * m, qq = q - base, half = base ? a.nr : m;
+                    if (w < count && qq < 2 * half && isfinite(sr) && isfinite(si)) {
+                        const int c = qq < half ? qq : qq - half;
                         const int p = i - (lo - m);
-                        const double ur = a.Bm[(int64_t)p * a.ldb + w * W + c];
-                        const double ui = a.Bm[(int64_t)p * a.ldb + w * W + m + c];
-                        v -= q < m ? (sr * ur - si * ui) : (sr * ui + si * ur);
+                        const double ur = a.Bm[(int64_t)p * a.ldb + w * W + base + c];
+                        const double ui = a.Bm[(int64_t)p * a.ldb + w * W + base + half + c];
+                        v -= qq < half ? (sr * ur - si * ui) : (sr * ui + si * ur);
                     }
                 }
                 a.Z[(int64_t)j * a.ldz + i] = v;

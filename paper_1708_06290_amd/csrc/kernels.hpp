@@ -41,11 +41,14 @@ bool launch_qstar(int m, bool dense_in, const QstarArgs<double> &a, hipStream_t 
 bool launch_qstar(int m, bool dense_in, const QstarArgs<float> &a, hipStream_t st);
 
 // Blocked FP64 sweep (blocked.hpp): row-tile height and per-shift column
-// width of the carried-column array; launchers.  false for an unsupported m.
-struct BlkTriArgs;
+// width of the carried-column array (with a dense right-hand side: m <=
+// kBlkDenseMaxM); launchers.  false for an unsupported m.
+template <typename T> struct BlkTriArgsT;
+using BlkTriArgs = BlkTriArgsT<double>;
 struct ZupdArgs;
-bool blk_geometry(int m, int *tile_rows, int *width);
-bool launch_blk_tri(int m, const BlkTriArgs &a, hipStream_t st);
+constexpr int kBlkDenseMaxM = 8;
+bool blk_geometry(int m, bool dense, int *tile_rows, int *width);
+bool launch_blk_tri(int m, bool dense, const BlkTriArgs &a, hipStream_t st);
 bool launch_zupd(int m, const ZupdArgs &a, hipStream_t st);
 
 }  // namespace shs

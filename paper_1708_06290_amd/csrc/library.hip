@@ -165,7 +165,7 @@ bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
     size_t end_blk = off, end_mix = off;
     {
         int tr = 0, w = 0;
-        if (!blk_geometry((int)m, &tr, &w)) return false;
+        if (!blk_geometry((int)m, false, &tr, &w)) return false;
         L->blocked = true;
         L->blk_cols = (w * s + 127) / 128 * 128;
         // rows of the block transforms, up to whole 16-row chunks
@@ -322,24 +322,60 @@ __global__ void mixed_final_kernel(const int *cfb, const int32_t *fb, const int3
     status[sid] = st != SHS_STATUS_OK ? st : (eta[sid] <= tol ? SHS_STATUS_FALLBACK : SHS_STATUS_NOT_CONVERGED);
 }
 
+// Buffers of the blocked sweep: carried columns Z (n x ncols), block
+// transforms Bm (blk_rows x ncols, row-major), per-shift carried matrices.
+struct BlkBuf {
+    double *Zb, *Bm, *M2, *M2p, *M2q;
+    int64_t blk_rows;
+};
+
+// Z(:, item W + 2m + c) + i Z(:, item W + 3m + c) = E_item(:, c) (the dense
+// right-hand side, E_v(i, c) at ((v m + c) n + i) 2) and every other column
+// of the item zero: the bottom tile reads e from Z and z from H.  Items past
+// count (the padding up to a whole 128 columns) are all zero: a 16-column
+// block of the update may hold several items, so every column it reads
+// must be finite.
+__global__ __launch_bounds__(256) void blk_dense_init_kernel(int n, int m, int W, int count, const double *E,
+                                                             double *Z, int64_t ldz)
+{
+    const int v = blockIdx.y, q = blockIdx.z;   // item, column within the item
+    double *z = Z + ((int64_t)v * W + q) * ldz;
+    const int c = q - 2 * m;
+    const bool re = v < count && c >= 0 && c < m, im = v < count && c >= m && c < 2 * m;
+    const double *src = E + ((int64_t)v * m + (re ? c : c - m)) * n * 2 + (re ? 0 : 1);
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+        z[i] = (re || im) ? src[2 * (int64_t)i] : 0.0;
+}
+
 // Blocked FP64 sweep of the listed shifts: per row tile (bottom to top) the
-// per-shift tile kernel, then the all-shift update of the rows above.
+// per-shift tile kernel, then the all-shift update of the rows above.  With
+// E set, the right-hand side is dense (m columns per shift, laid out as for
+// blk_dense_init_kernel, m <= kBlkDenseMaxM) and the matrix is Hm (H or its
+// order-reversed transpose).
 hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, const int *dcount, const double *shifts,
-                         void *work, const Layout &L, const SweepArgs<double> &sa, hipStream_t st)
+                         const BlkBuf &B, const SweepArgs<double> &sa, hipStream_t st, const double *E = nullptr,
+                         const double *Hm = nullptr)
 {
     const int n = (int)h->n, m = (int)h->m;
+    const bool dense = E != nullptr;
+    if (!Hm) Hm = h->H;
     int tr = 0, w = 0;
-    if (!blk_geometry(m, &tr, &w)) return hipErrorInvalidValue;
+    if (!blk_geometry(m, dense, &tr, &w)) return hipErrorInvalidValue;
     if (count <= 0) return hipSuccess;
     const int ntiles = (n + tr - 1) / tr;
     const int64_t ncols = (w * count + 127) / 128 * 128;
-    double *Zb = at<double>(work, L.zb), *Bm = at<double>(work, L.bm), *M2 = at<double>(work, L.m2);
-    double *M2p = at<double>(work, L.m2p), *M2q = at<double>(work, L.m2q);
+    double *Zb = B.Zb, *Bm = B.Bm, *M2 = B.M2, *M2p = B.M2p, *M2q = B.M2q;
     PhaseScope whole(h, PH_SWEEP, count, st);
+    if (dense) {
+        hipLaunchKernelGGL(blk_dense_init_kernel, dim3(cdiv(n, 256 * 8), (unsigned)(ncols / w), (unsigned)w),
+                           dim3(256), 0, st, n, m, w, (int)count, E, Zb, (int64_t)n);
+        const hipError_t e0 = hipGetLastError();
+        if (e0 != hipSuccess) return e0;
+    }
     // columns past 2m of each shift, those of the padding shifts and the
     // rows past the bottom tile's K stay zero.  Bm is row-major with row
     // stride ncols.
-    hipError_t e = zero_fill(Bm, sizeof(double) * L.blk_rows * ncols, st);
+    hipError_t e = zero_fill(Bm, sizeof(double) * B.blk_rows * ncols, st);
     if (e != hipSuccess) return e;
     e = zero_fill(M2, sizeof(double) * (ncols / w) * w * w, st);
     if (e != hipSuccess) return e;
@@ -351,7 +387,7 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     ta.n = n;
     ta.count = (int)count;
     ta.ntiles = ntiles;
-    ta.H = h->H;
+    ta.H = Hm;
     ta.ldh = h->ldh;
     ta.shifts = shifts;
     ta.list = dlist;
@@ -373,7 +409,8 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     za.n = n;
     za.ncols = (int)ncols;
     za.count = (int)count;
-    za.H = h->H;
+    za.nr = dense ? m : 0;
+    za.H = Hm;
     za.ldh = h->ldh;
     za.Bm = Bm;
     za.ldb = ncols;
@@ -397,15 +434,17 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
         ta.M2q = m2nxt;
         {
             PhaseScope ps(h, PH_TILE, count, st);
-            if (!launch_blk_tri(m, ta, st)) return hipErrorInvalidValue;
+            if (!launch_blk_tri(m, dense, ta, st)) return hipErrorInvalidValue;
         }
         if (h->timing && !dcount) {   // timing state is only touched when enabled (flops: host-known counts only)
             // steps: (16m+4) flops per row above the pivot in the tile; the
             // block transform: n_b reflectors on m columns of length m+1; a
             // group's k-th tile: its older composite rows and M2 times 2m x 2m
-            const double nb = std::min(n, t * tr + tr) - t * tr, w2 = 2.0 * m;
-            double f = (16.0 * m + 4.0) * nb * (nb - 1.0) / 2.0;
-            if (t > 0) f += 16.0 * (m + 1) * m * nb;
+            // (a dense right-hand side: the e updates inside the tile, N_blk
+            // beside M_blk, and 4m x 4m carried matrices)
+            const double nb = std::min(n, t * tr + tr) - t * tr, w2 = (dense ? 4.0 : 2.0) * m;
+            double f = ((dense ? 24.0 : 16.0) * m + 4.0) * nb * (nb - 1.0) / 2.0;
+            if (t > 0) f += 16.0 * (m + 1) * (dense ? 2 * m : m) * nb;
             if (t > 0 && k >= 2) f += 2.0 * ((k - 1) * tr + w2) * w2 * w2;
             h->tile_flops += f * (double)count;
         }
@@ -417,7 +456,7 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
         if (bottom) {
             za.r0 = 0;
             za.K = hi - lo + m;
-            za.has_zin = 0;
+            za.has_zin = dense ? 1 : 0;   // a dense right-hand side is carried in Z from the start
             za.Bm = Bm;
             za.M2 = M2;
         } else if (k < kBlkGroup) {
@@ -442,7 +481,8 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
         // 2m x 2m matrix when carried columns are read
         if (h->timing && !dcount)
             h->update_flops +=
-                (2.0 * (za.lo - za.r0) * za.K * 2 * m + (za.has_zin ? 2.0 * (za.lo - za.r0) * 4.0 * m * m : 0.0)) *
+                (2.0 * (za.lo - za.r0) * za.K * (dense ? 4 : 2) * m +
+                 (za.has_zin ? 2.0 * (za.lo - za.r0) * 2.0 * m * (dense ? 4 : 2) * m : 0.0)) *
                 (double)count;
     }
     return hipGetLastError();
@@ -495,7 +535,9 @@ hipError_t solve_fp64(shs_handle *h, int64_t count, const int32_t *dlist, const 
     sa.status = status;
     sa.dcount = dcount;
     if (L.blocked) {
-        hipError_t e = sweep_blocked(h, count, dlist, dcount, shifts, work, L, sa, st);
+        const BlkBuf B{at<double>(work, L.zb), at<double>(work, L.bm), at<double>(work, L.m2),
+                       at<double>(work, L.m2p), at<double>(work, L.m2q), L.blk_rows};
+        hipError_t e = sweep_blocked(h, count, dlist, dcount, shifts, B, sa, st);
         if (e != hipSuccess) return e;
     } else {
         PhaseScope ps(h, PH_SWEEP, count, st);
@@ -670,6 +712,9 @@ __global__ __launch_bounds__(256) void transposed_unpack_kernel(int n, int m, in
 
 struct TransLayout {
     size_t shv = 0, e = 0, yd = 0, refl = 0, xv = 0, stv = 0, etav = 0, resmax = 0, xmax = 0, emax = 0, xt = 0;
+    size_t zb = 0, bm = 0, m2 = 0, m2p = 0, m2q = 0;   // blocked sweep (m <= kBlkDenseMaxM)
+    bool blocked = false;
+    int64_t blk_rows = 0;
     size_t total = 0;
     int64_t nch = 0, nv = 0, refl_stride = 0;
 };
@@ -696,6 +741,19 @@ bool trans_layout(const shs_handle *h, int64_t s, int64_t r, TransLayout *L)
     L->xmax = take(sizeof(unsigned long long) * m * nv);
     L->emax = take(sizeof(unsigned long long) * m * nv);
     L->xt = take(sizeof(double) * residual_pack_rows(n) * residual_pack_ld(m * nv));
+    int tr = 0, w = 0;
+    if (blk_geometry((int)m, true, &tr, &w)) {
+        // the blocked sweep with a dense right-hand side (Section 3.1, Step 2
+        // revisited, with N_blk beside M_blk)
+        L->blocked = true;
+        const int64_t cols = (w * nv + 127) / 128 * 128;
+        L->blk_rows = (kBlkGroup * tr + m + 15) / 16 * 16;
+        L->zb = take(sizeof(double) * n * cols);
+        L->bm = take(sizeof(double) * L->blk_rows * cols);
+        L->m2 = take(sizeof(double) * (cols / w) * w * w);
+        L->m2p = take(sizeof(double) * (cols / w) * w * w);
+        L->m2q = take(sizeof(double) * (cols / w) * w * w);
+    }
     L->total = off;
     return true;
 }
@@ -1580,7 +1638,11 @@ static int transposed_impl(shs_handle *h, int64_t s, const double *shifts, int64
         da.Y = at<double>(work, L.yd);
         da.y_stride = 2 * n * m;
         da.status = stv;
-        {
+        if (L.blocked) {
+            const BlkBuf B{at<double>(work, L.zb), at<double>(work, L.bm), at<double>(work, L.m2),
+                           at<double>(work, L.m2p), at<double>(work, L.m2q), L.blk_rows};
+            e = sweep_blocked(h, nv, nullptr, nullptr, shv, B, da, st, E, h->Ht);
+        } else {
             PhaseScope ps(h, PH_SWEEP, nv, st);
             if (!launch_sweep((int)m, true, da, st)) e = hipErrorInvalidValue;
         }

@@ -115,10 +115,21 @@ using BlkTriArgs = BlkTriArgsT<double>;
 // the carried matrix [[M2, -N2], [0, I]], which maps [z e] to
 // [z M2, e - z N2]; the bottom tile folds M2 and -N2 into K and carries e
 // through the identity.
+// Rows per lane of the tile kernels: the per-shift sweep's choice in FP64;
+// in FP32 at most 4 (with 8 the step body unrolled per row slot no longer fits
+// the registers and spills up to a kilobyte per lane).
+template <typename T, int M, bool DENSE>
+__host__ __device__ constexpr int blk_rb()
+{
+    constexpr int r = rows_per_lane<T, M, DENSE>();
+    return sizeof(T) == 4 && r > 4 ? 4 : r;
+}
+
 template <typename T, int M, bool DENSE>
 __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
 {
-    using Sh = SweepShape<T, M, DENSE>;
+    constexpr int RB = blk_rb<T, M, DENSE>();
+    using Sh = SweepShape<T, M, DENSE, RB>;
     constexpr int R = Sh::R, TT = Sh::TT, S = Sh::S, NP = Sh::NP, EM = Sh::EM;
     constexpr int W = blk_cols(M, DENSE);
     constexpr int AW = DENSE ? 4 * M : 2 * M;   // active real columns per shift
@@ -191,8 +202,8 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
     }
 
     bool singular = false, nonfinite = false;
-    tri_phase<T, M, DENSE, true>(n, lo, hi, lane, H, ldh, sgr, sgi, rf, tstride, Y, lds_rs, wr, wi, er, ei, singular,
-                                 nonfinite);
+    tri_phase<T, M, DENSE, true, RB>(n, lo, hi, lane, H, ldh, sgr, sgi, rf, tstride, Y, lds_rs, wr, wi, er, ei,
+                                     singular, nonfinite);
     // the tile's reflector stores complete before they are read back below
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 
@@ -400,7 +411,8 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
     }
 }
 
-struct ZupdArgs {
+template <typename T>
+struct ZupdArgsT {
     int r0;                    // rows r0 .. lo-1 are updated (r0 and lo even, lo - r0 >= 2)
     int lo;
     int c0;                    // first column of H in the block (lo - m)
@@ -411,17 +423,18 @@ struct ZupdArgs {
     int ncols;                 // columns of Z (W per work item, a multiple of 128)
     int count;                 // work items
     int has_zin;               // 0 for the bottom tile (no carried columns in Z yet)
-    const double *H;           // ld ldh, even, 16-byte aligned columns
+    const T *H;                // ld ldh, 16-byte aligned columns
     int64_t ldh;
-    const double *Bm;          // row-major, row stride ldb; rows K .. K rounded up to 16 are zero
+    const T *Bm;               // row-major, row stride ldb; rows K .. K rounded up to 16 are zero
     int64_t ldb;
-    const double *M2;
-    double *Z;
+    const T *M2;
+    T *Z;
     int64_t ldz;
     const double *shifts;
     const int32_t *list;
     const int *dcount;         // if set, the number of work items is read here (count is an upper bound)
 };
+using ZupdArgs = ZupdArgsT<double>;
 
 typedef double zupd_dbl4 __attribute__((ext_vector_type(4)));
 
@@ -456,7 +469,7 @@ constexpr int kZupdLds = 2 * 2 * 16 * 128 * (int)sizeof(double);
 // chunk's fragments are in registers and waited for only after its 64
 // MFMAs.
 template <int W>
-__global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgs a)
+__global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgsT<double> a)
 {
     constexpr int BM = 128, BN = 128, BK = 16;
     extern __shared__ double zupd_smem[];
@@ -600,6 +613,163 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgs a)
                         const int p = i - (lo - m);
                         const double ur = a.Bm[(int64_t)p * a.ldb + w * W + base + c];
                         const double ui = a.Bm[(int64_t)p * a.ldb + w * W + base + half + c];
+                        v -= qq < half ? (sr * ur - si * ui) : (sr * ui + si * ur);
+                    }
+                }
+                a.Z[(int64_t)j * a.ldz + i] = v;
+            }
+}
+
+
+// FP32 form of zupd_kernel for the mixed-precision sweep: the same tiling,
+// schedule and direct-to-LDS operand streaming, on H32 with
+// v_mfma_f32_16x16x4f32 (twice the FP64 matrix rate).  Each direct-to-LDS
+// load moves four consecutive floats per lane, so one instruction fills two
+// k-rows of a chunk (lanes 0-31 the first, 32-63 the second).  The result
+// layout of the FP32 instruction differs from the FP64 one: register r of
+// lane l holds D(4 (l/16) + r, l%16).
+typedef float zupd_flt4 __attribute__((ext_vector_type(4)));
+constexpr int kZupd32Lds = 2 * 2 * 16 * 128 * (int)sizeof(float);
+
+template <int W>
+__global__ __launch_bounds__(256, 2) void zupd32_kernel(ZupdArgsT<float> a)
+{
+    constexpr int BM = 128, BN = 128, BK = 16;
+    extern __shared__ float zupd32_smem[];
+    auto As = reinterpret_cast<float (*)[BK][BM]>(zupd32_smem);
+    auto Bs = reinterpret_cast<float (*)[BK][BN]>(zupd32_smem + 2 * BK * BM);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lo = a.lo, K = a.K;
+    int i0, j0;
+    {
+        const int nx = a.ncols / BN, ny = (lo - a.r0 + BM - 1) / BM, T = nx * ny;
+        const int L = blockIdx.x, xcd = L & 7, li = L >> 3;
+        const int per = T >> 3, rem = T & 7;
+        const int g = xcd * per + min(xcd, rem) + li;
+        constexpr int GR = 8;
+        const int grp = g / (GR * nx), r = g - grp * GR * nx;
+        const int rows = min(GR, ny - grp * GR);
+        i0 = a.r0 + (grp * GR + r % rows) * BM;
+        j0 = (r / rows) * BN;
+    }
+    const int count = a.dcount ? *a.dcount : a.count;
+    if (j0 >= count * W) return;
+
+    zupd_flt4 acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = zupd_flt4{0.f, 0.f, 0.f, 0.f};
+
+    // ---- carried part: Z(rows, shift) * M2(shift) ------------------------------
+    if (a.has_zin) {
+        constexpr int KZ = W > 16 ? W : 16;
+        constexpr int NS = KZ / 4;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            float az[2][4][NS], bz[2][NS];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int nt = 2 * half + h;
+                const int cb = j0 + wc * 64 + nt * 16;
+                const int zc = W <= 16 ? cb : (cb / W) * W;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const int k = 4 * s + lane / 16, q = lane % 16;
+                    if constexpr (W <= 16) {
+                        const int sk = (cb + k) / W, sq = (cb + q) / W;
+                        bz[h][s] = sk == sq ? a.M2[(int64_t)sk * W * W + ((cb + k) % W) * W + (cb + q) % W] : 0.f;
+                    } else {
+                        bz[h][s] = a.M2[(int64_t)(cb / W) * W * W + k * W + cb % W + q];
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt) {
+                        const int i = i0 + wr * 64 + mt * 16 + lane % 16;
+                        az[h][mt][s] = i < lo ? a.Z[(int64_t)(zc + k) * a.ldz + i] : 0.f;
+                    }
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                    for (int s = 0; s < NS; ++s)
+                        acc[mt][2 * half + h] =
+                            __builtin_amdgcn_mfma_f32_16x16x4f32(az[h][mt][s], bz[h][s], acc[mt][2 * half + h], 0, 0, 0);
+        }
+    }
+
+    // ---- main product: H(0:lo, c0 : c0+K) Bm -----------------------------------
+    // wave w moves k-rows 4w .. 4w+3 of each chunk of both operands, two per
+    // instruction (lane l: k-row 4w + 2e + l/32, elements 4 (l%32) .. + 3)
+    const int hk = lane >> 5, p4 = 4 * (lane & 31);
+    const int ia = min(i0 + p4, lo - 4);
+    const float *pa = a.H + ia;
+    const float *pb = a.Bm + j0 + p4;
+    auto issue = [&](int b, int k0) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int k = 4 * wave + 2 * e + hk;
+            const int col = min(a.c0 + k0 + k, a.n - 1);
+            __builtin_amdgcn_global_load_lds((const void *)(pa + (int64_t)col * a.ldh),
+                                             (__attribute__((address_space(3))) void *)&As[b][4 * wave + 2 * e][0], 16,
+                                             0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(pb + (int64_t)(k0 + k) * a.ldb),
+                                             (__attribute__((address_space(3))) void *)&Bs[b][4 * wave + 2 * e][0], 16,
+                                             0, 0);
+        }
+    };
+    const int nk = (K + BK - 1) / BK;
+    if (nk > 0) issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0x0070);   // vmcnt(0) lgkmcnt(0)
+    __syncthreads();
+    for (int it = 0; it < nk; ++it) {
+        const int b = it & 1;
+        float af[4][4], bf[4][4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) af[s][mt] = As[b][4 * s + lane / 16][wr * 64 + mt * 16 + lane % 16];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) bf[s][nt] = Bs[b][4 * s + lane / 16][wc * 64 + nt * 16 + lane % 16];
+        }
+        if (it + 1 < nk) issue(b ^ 1, (it + 1) * BK);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s][mt], bf[s][nt], acc[mt][nt], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0x0070);
+        __syncthreads();
+    }
+
+    // ---- epilogue: sigma on the block's diagonal rows, store ----------------
+    const int m = a.m;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wr * 64 + mt * 16 + 4 * (lane / 16) + r;
+                const int j = j0 + wc * 64 + nt * 16 + lane % 16;
+                if (i >= lo) continue;
+                float v = acc[mt][nt][r];
+                if (i >= lo - m) {
+                    const int w = j / W, q = j % W;
+                    const int sid = w < count ? (a.list ? a.list[w] : w) : 0;
+                    const float sr = (float)a.shifts[2 * sid], si = (float)a.shifts[2 * sid + 1];
+                    const int base = q < 2 * m ? 0 : 2 * m, qq = q - base, half = base ? a.nr : m;
+                    if (w < count && qq < 2 * half && isfinite(sr) && isfinite(si)) {
+                        const int c = qq < half ? qq : qq - half;
+                        const int p = i - (lo - m);
+                        const float ur = a.Bm[(int64_t)p * a.ldb + w * W + base + c];
+                        const float ui = a.Bm[(int64_t)p * a.ldb + w * W + base + half + c];
                         v -= qq < half ? (sr * ur - si * ui) : (sr * ui + si * ur);
                     }
                 }

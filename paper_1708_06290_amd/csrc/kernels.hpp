@@ -45,11 +45,14 @@ bool launch_qstar(int m, bool dense_in, const QstarArgs<float> &a, hipStream_t s
 // kBlkDenseMaxM); launchers.  false for an unsupported m.
 template <typename T> struct BlkTriArgsT;
 using BlkTriArgs = BlkTriArgsT<double>;
-struct ZupdArgs;
+template <typename T> struct ZupdArgsT;
+using ZupdArgs = ZupdArgsT<double>;
 constexpr int kBlkDenseMaxM = 8;
-bool blk_geometry(int m, bool dense, int *tile_rows, int *width);
-bool launch_blk_tri(int m, bool dense, const BlkTriArgs &a, hipStream_t st);
-bool launch_zupd(int m, const ZupdArgs &a, hipStream_t st);
+bool blk_geometry(bool fp32, int m, bool dense, int *tile_rows, int *width);
+bool launch_blk_tri(int m, bool dense, const BlkTriArgsT<double> &a, hipStream_t st);
+bool launch_blk_tri(int m, bool dense, const BlkTriArgsT<float> &a, hipStream_t st);
+bool launch_zupd(int m, const ZupdArgsT<double> &a, hipStream_t st);
+bool launch_zupd(int m, const ZupdArgsT<float> &a, hipStream_t st);
 
 }  // namespace shs
 

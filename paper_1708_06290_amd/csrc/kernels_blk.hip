@@ -6,19 +6,22 @@
 
 namespace shs {
 
-bool blk_geometry(int m, bool dense, int *tile_rows, int *width)
+bool blk_geometry(bool fp32, int m, bool dense, int *tile_rows, int *width)
 {
     if (dense && m > kBlkDenseMaxM) return false;
     bool ok = false;
     SHS_DISPATCH_M(m, {
-        *tile_rows = dense ? SweepShape<double, MM, true>::TT : SweepShape<double, MM, false>::TT;
+        if (fp32)
+            *tile_rows = dense ? kWave * blk_rb<float, MM, true>() : kWave * blk_rb<float, MM, false>();
+        else
+            *tile_rows = dense ? kWave * blk_rb<double, MM, true>() : kWave * blk_rb<double, MM, false>();
         *width = blk_cols(MM, dense);
         ok = true;
     });
     return ok;
 }
 
-bool launch_blk_tri(int m, bool dense, const BlkTriArgs &a, hipStream_t st)
+bool launch_blk_tri(int m, bool dense, const BlkTriArgsT<double> &a, hipStream_t st)
 {
     bool ok = false;
     if (!dense) {
@@ -42,16 +45,23 @@ bool launch_blk_tri(int m, bool dense, const BlkTriArgs &a, hipStream_t st)
     return ok;
 }
 
-bool launch_zupd(int m, const ZupdArgs &a, hipStream_t st)
+// What the direct-to-LDS loads assume: 16-byte aligned groups of rows of H
+// and of columns of Bm (two doubles or four floats), at least one group of
+// rows, K a whole number of chunks unless the padding rows of Bm are zero
+// (the bottom tile).
+template <typename T>
+static bool zupd_args_ok(int m, const ZupdArgsT<T> &a)
+{
+    constexpr int G = 16 / (int)sizeof(T);
+    return !((a.r0 | a.lo) % G || a.lo - a.r0 < G || a.ldh % G || a.ldb % G || a.ncols % 128 != 0 || a.c0 < 0 ||
+             (a.has_zin && a.K % 16 != 0 && a.nr == 0) || a.K <= 0 || a.n < a.lo ||
+             ((uintptr_t)a.H | (uintptr_t)a.Bm) & 15 || (a.nr != 0 && a.nr != m));
+}
+
+bool launch_zupd(int m, const ZupdArgsT<double> &a, hipStream_t st)
 {
     if (a.lo <= a.r0) return true;
-    // what the direct-to-LDS loads assume: 16-byte aligned pairs of rows of
-    // H and of columns of Bm, at least two rows, K a whole number of chunks
-    // unless the padding rows of Bm are zero (the bottom tile)
-    if ((a.r0 | a.lo) & 1 || a.lo - a.r0 < 2 || a.ldh & 1 || a.ldb & 1 || a.ncols % 128 != 0 || a.c0 < 0 ||
-        (a.has_zin && a.K % 16 != 0 && a.nr == 0) || a.K <= 0 || a.n < a.lo ||
-        ((uintptr_t)a.H | (uintptr_t)a.Bm) & 15 || (a.nr != 0 && a.nr != m))
-        return false;
+    if (!zupd_args_ok(m, a)) return false;
     const dim3 grid((unsigned)((a.ncols / 128) * ((a.lo - a.r0 + 127) / 128)));
     switch (blk_cols(m, a.nr != 0)) {
     case 2: hipLaunchKernelGGL((zupd_kernel<2>), grid, dim3(256), kZupdLds, st, a); return true;
@@ -59,6 +69,21 @@ bool launch_zupd(int m, const ZupdArgs &a, hipStream_t st)
     case 8: hipLaunchKernelGGL((zupd_kernel<8>), grid, dim3(256), kZupdLds, st, a); return true;
     case 16: hipLaunchKernelGGL((zupd_kernel<16>), grid, dim3(256), kZupdLds, st, a); return true;
     case 32: hipLaunchKernelGGL((zupd_kernel<32>), grid, dim3(256), kZupdLds, st, a); return true;
+    default: return false;
+    }
+}
+
+bool launch_zupd(int m, const ZupdArgsT<float> &a, hipStream_t st)
+{
+    if (a.lo <= a.r0) return true;
+    if (!zupd_args_ok(m, a)) return false;
+    const dim3 grid((unsigned)((a.ncols / 128) * ((a.lo - a.r0 + 127) / 128)));
+    switch (blk_cols(m, a.nr != 0)) {
+    case 2: hipLaunchKernelGGL((zupd32_kernel<2>), grid, dim3(256), kZupd32Lds, st, a); return true;
+    case 4: hipLaunchKernelGGL((zupd32_kernel<4>), grid, dim3(256), kZupd32Lds, st, a); return true;
+    case 8: hipLaunchKernelGGL((zupd32_kernel<8>), grid, dim3(256), kZupd32Lds, st, a); return true;
+    case 16: hipLaunchKernelGGL((zupd32_kernel<16>), grid, dim3(256), kZupd32Lds, st, a); return true;
+    case 32: hipLaunchKernelGGL((zupd32_kernel<32>), grid, dim3(256), kZupd32Lds, st, a); return true;
     default: return false;
     }
 }

@@ -131,6 +131,12 @@ struct Layout {
     size_t zb = 0, bm = 0, m2 = 0, m2p = 0, m2q = 0;
     size_t xt = 0;   // packed solutions for the residual
     int64_t blk_rows = 0, blk_cols = 0;
+    // blocked FP32 sweeps of the mixed mode (structured; dense corrections
+    // when blk32_dense): their carried columns, block transforms and
+    // carried matrices, and the reflector-store stride per shift
+    size_t z32 = 0, bm32 = 0, m2a = 0, m2b = 0, m2c = 0;
+    int64_t blk32_rows = 0, refl32_stride = 0;
+    bool blk32_dense = false;
     size_t total = 0;
 };
 
@@ -165,7 +171,7 @@ bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
     size_t end_blk = off, end_mix = off;
     {
         int tr = 0, w = 0;
-        if (!blk_geometry((int)m, false, &tr, &w)) return false;
+        if (!blk_geometry(false, (int)m, false, &tr, &w)) return false;
         L->blocked = true;
         L->blk_cols = (w * s + 127) / 128 * 128;
         // rows of the block transforms, up to whole 16-row chunks
@@ -180,7 +186,22 @@ bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
     if (mode == SHS_MODE_FP32_REFINE) {
         off = region;
         if (!geo(true, n, m, false, &g32s) || !geo(true, n, m, true, &g32d)) return false;
-        L->refl32 = take(sizeof(float) * std::max(g32s.stride, g32d.stride) * s);
+        int trs = 0, ws = 0, trd = 0, wd = 0;
+        if (!blk_geometry(true, (int)m, false, &trs, &ws)) return false;
+        L->blk32_dense = blk_geometry(true, (int)m, true, &trd, &wd);
+        const int64_t wmax = std::max(ws, wd), cols = (wmax * s + 127) / 128 * 128;
+        const int64_t st_s = (n + trs - 1) / trs * refl_tile_stride<float>(trs, slot_elems((int)m, false));
+        const int64_t st_d = L->blk32_dense
+                                 ? (n + trd - 1) / trd * refl_tile_stride<float>(trd, slot_elems((int)m, true))
+                                 : g32d.stride;
+        L->refl32_stride = std::max(st_s, st_d);
+        L->refl32 = take(sizeof(float) * L->refl32_stride * s);
+        L->blk32_rows = (kBlkGroup * std::max(trs, trd) + m + 15) / 16 * 16;
+        L->z32 = take(sizeof(float) * n * cols);
+        L->bm32 = take(sizeof(float) * L->blk32_rows * cols);
+        L->m2a = take(sizeof(float) * cols * wmax);
+        L->m2b = take(sizeof(float) * cols * wmax);
+        L->m2c = take(sizeof(float) * cols * wmax);
         L->y32 = take(sizeof(float) * 2 * m * m * s);
         L->e32 = take(sizeof(float) * 2 * n * m * s);
         L->yd32 = take(sizeof(float) * 2 * n * m * s);
@@ -324,66 +345,74 @@ __global__ void mixed_final_kernel(const int *cfb, const int32_t *fb, const int3
 
 // Buffers of the blocked sweep: carried columns Z (n x ncols), block
 // transforms Bm (blk_rows x ncols, row-major), per-shift carried matrices.
-struct BlkBuf {
-    double *Zb, *Bm, *M2, *M2p, *M2q;
+template <typename T>
+struct BlkBufT {
+    T *Zb, *Bm, *M2, *M2p, *M2q;
     int64_t blk_rows;
 };
+using BlkBuf = BlkBufT<double>;
 
-// Z(:, item W + 2m + c) + i Z(:, item W + 3m + c) = E_item(:, c) (the dense
-// right-hand side, E_v(i, c) at ((v m + c) n + i) 2) and every other column
-// of the item zero: the bottom tile reads e from Z and z from H.  Items past
-// count (the padding up to a whole 128 columns) are all zero: a 16-column
-// block of the update may hold several items, so every column it reads
-// must be finite.
-__global__ __launch_bounds__(256) void blk_dense_init_kernel(int n, int m, int W, int count, const double *E,
-                                                             double *Z, int64_t ldz)
+// Z(:, item W + 2m + c) + i Z(:, item W + 3m + c) = E_sid(:, c) (the dense
+// right-hand side of the item's shift, E_sid(i, c) at ((sid m + c) n + i) 2)
+// and every other column of the item zero: the bottom tile reads e from Z and
+// z from H.  Items past the list (and the padding up to a whole 128 columns)
+// are all zero: a 16-column block of the update may hold several items, so
+// every column it reads must be finite.
+template <typename T>
+__global__ __launch_bounds__(256) void blk_dense_init_kernel(int n, int m, int W, int count, const int *dcount,
+                                                             const int32_t *list, const T *E, T *Z, int64_t ldz)
 {
     const int v = blockIdx.y, q = blockIdx.z;   // item, column within the item
-    double *z = Z + ((int64_t)v * W + q) * ldz;
+    const int cnt = dcount ? *dcount : count;
+    T *z = Z + ((int64_t)v * W + q) * ldz;
     const int c = q - 2 * m;
-    const bool re = v < count && c >= 0 && c < m, im = v < count && c >= m && c < 2 * m;
-    const double *src = E + ((int64_t)v * m + (re ? c : c - m)) * n * 2 + (re ? 0 : 1);
+    const bool re = v < cnt && c >= 0 && c < m, im = v < cnt && c >= m && c < 2 * m;
+    const int sid = v < cnt ? (list ? list[v] : v) : 0;
+    const T *src = E + ((int64_t)sid * m + (re ? c : c - m)) * n * 2 + (re ? 0 : 1);
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
-        z[i] = (re || im) ? src[2 * (int64_t)i] : 0.0;
+        z[i] = (re || im) ? src[2 * (int64_t)i] : T(0);
 }
 
-// Blocked FP64 sweep of the listed shifts: per row tile (bottom to top) the
-// per-shift tile kernel, then the all-shift update of the rows above.  With
-// E set, the right-hand side is dense (m columns per shift, laid out as for
-// blk_dense_init_kernel, m <= kBlkDenseMaxM) and the matrix is Hm (H or its
-// order-reversed transpose).
+// Blocked sweep of the listed shifts (FP64 on H, or FP32 on H32 for the
+// mixed form): per row tile (bottom to top) the per-shift tile kernel, then
+// the all-shift update of the rows above.  With E set, the right-hand side
+// is dense (m columns per shift id, laid out as for blk_dense_init_kernel,
+// m <= kBlkDenseMaxM) and the matrix is Hm (H, H32 or H's order-reversed
+// transpose).  ph: the timing phase of the whole sweep.
+template <typename T>
 hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, const int *dcount, const double *shifts,
-                         const BlkBuf &B, const SweepArgs<double> &sa, hipStream_t st, const double *E = nullptr,
-                         const double *Hm = nullptr)
+                         const BlkBufT<T> &B, const SweepArgs<T> &sa, hipStream_t st, const T *E = nullptr,
+                         const T *Hm = nullptr, int ph = PH_SWEEP)
 {
     const int n = (int)h->n, m = (int)h->m;
     const bool dense = E != nullptr;
-    if (!Hm) Hm = h->H;
+    constexpr bool fp32 = sizeof(T) == 4;
+    if (!Hm) Hm = fp32 ? (const T *)(const void *)h->H32 : (const T *)(const void *)h->H;
     int tr = 0, w = 0;
-    if (!blk_geometry(m, dense, &tr, &w)) return hipErrorInvalidValue;
+    if (!blk_geometry(fp32, m, dense, &tr, &w)) return hipErrorInvalidValue;
     if (count <= 0) return hipSuccess;
     const int ntiles = (n + tr - 1) / tr;
     const int64_t ncols = (w * count + 127) / 128 * 128;
-    double *Zb = B.Zb, *Bm = B.Bm, *M2 = B.M2, *M2p = B.M2p, *M2q = B.M2q;
-    PhaseScope whole(h, PH_SWEEP, count, st);
+    T *Zb = B.Zb, *Bm = B.Bm, *M2 = B.M2, *M2p = B.M2p, *M2q = B.M2q;
+    PhaseScope whole(h, ph, count, st);
     if (dense) {
-        hipLaunchKernelGGL(blk_dense_init_kernel, dim3(cdiv(n, 256 * 8), (unsigned)(ncols / w), (unsigned)w),
-                           dim3(256), 0, st, n, m, w, (int)count, E, Zb, (int64_t)n);
+        hipLaunchKernelGGL(blk_dense_init_kernel<T>, dim3(cdiv(n, 256 * 8), (unsigned)(ncols / w), (unsigned)w),
+                           dim3(256), 0, st, n, m, w, (int)count, dcount, dlist, E, Zb, (int64_t)n);
         const hipError_t e0 = hipGetLastError();
         if (e0 != hipSuccess) return e0;
     }
     // columns past 2m of each shift, those of the padding shifts and the
     // rows past the bottom tile's K stay zero.  Bm is row-major with row
     // stride ncols.
-    hipError_t e = zero_fill(Bm, sizeof(double) * B.blk_rows * ncols, st);
+    hipError_t e = zero_fill(Bm, sizeof(T) * B.blk_rows * ncols, st);
     if (e != hipSuccess) return e;
-    e = zero_fill(M2, sizeof(double) * (ncols / w) * w * w, st);
+    e = zero_fill(M2, sizeof(T) * (ncols / w) * w * w, st);
     if (e != hipSuccess) return e;
-    e = zero_fill(M2p, sizeof(double) * (ncols / w) * w * w, st);
+    e = zero_fill(M2p, sizeof(T) * (ncols / w) * w * w, st);
     if (e != hipSuccess) return e;
-    e = zero_fill(M2q, sizeof(double) * (ncols / w) * w * w, st);
+    e = zero_fill(M2q, sizeof(T) * (ncols / w) * w * w, st);
     if (e != hipSuccess) return e;
-    BlkTriArgs ta{};
+    BlkTriArgsT<T> ta{};
     ta.n = n;
     ta.count = (int)count;
     ta.ntiles = ntiles;
@@ -404,7 +433,7 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     ta.M2 = M2;
     ta.D = kBlkGroup;
     ta.dcount = dcount;
-    ZupdArgs za{};
+    ZupdArgsT<T> za{};
     za.m = m;
     za.n = n;
     za.ncols = (int)ncols;
@@ -424,7 +453,7 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     // groups of kBlkGroup tiles: after the k-th, the next tile's rows get the
     // group's composite (K = k n_b); after the last, all rows above do
     int k = 0;
-    double *m2cur = M2p, *m2nxt = M2q;   // composite M2: read, written
+    T *m2cur = M2p, *m2nxt = M2q;   // composite M2: read, written
     for (int t = ntiles - 1; t >= 0; --t) {
         const bool bottom = t == ntiles - 1;
         ta.t = t;
@@ -742,7 +771,7 @@ bool trans_layout(const shs_handle *h, int64_t s, int64_t r, TransLayout *L)
     L->emax = take(sizeof(unsigned long long) * m * nv);
     L->xt = take(sizeof(double) * residual_pack_rows(n) * residual_pack_ld(m * nv));
     int tr = 0, w = 0;
-    if (blk_geometry((int)m, true, &tr, &w)) {
+    if (blk_geometry(false, (int)m, true, &tr, &w)) {
         // the blocked sweep with a dense right-hand side (Section 3.1, Step 2
         // revisited, with N_blk beside M_blk)
         L->blocked = true;
@@ -1052,23 +1081,28 @@ hipError_t solve_mixed(shs_handle *h, int64_t s, const double *shifts, double to
     sa.list = nullptr;
     sa.Rtop = h->Rtop;
     sa.refl = at<float>(work, L.refl32);
-    sa.refl_stride = g32s.stride;
+    sa.refl_stride = L.refl32_stride;
     sa.Y = at<float>(work, L.y32);
     sa.y_stride = 2 * m * m;
     sa.status = st2;
-    {
-        PhaseScope ps(h, PH_SWEEP32, s, st);
-        if (!launch_sweep((int)m, false, sa, st)) return hipErrorInvalidValue;
-    }
+    // the FP32 sweeps run blocked (Section 3.1, Step 2 revisited) on the FP32
+    // matrix cores; their reflector stores follow the blocked tile height
+    const BlkBufT<float> B32{at<float>(work, L.z32), at<float>(work, L.bm32), at<float>(work, L.m2a),
+                             at<float>(work, L.m2b), at<float>(work, L.m2c), L.blk32_rows};
+    int trs = 0, ws = 0, trd = 0, wd = 0;
+    blk_geometry(true, (int)m, false, &trs, &ws);
+    blk_geometry(true, (int)m, true, &trd, &wd);
+    e = sweep_blocked<float>(h, s, nullptr, nullptr, shifts, B32, sa, st, nullptr, h->H32, PH_SWEEP32);
+    if (e != hipSuccess) return e;
     QstarArgs<float> qa{};
     qa.n = (int)n;
     qa.count = (int)s;
     qa.list = nullptr;
     qa.refl = sa.refl;
-    qa.refl_stride = g32s.stride;
-    qa.tile_rows = g32s.g.tile_rows;
-    qa.tile_stride = g32s.g.tile_stride;
-    qa.slot = g32s.g.slot;
+    qa.refl_stride = L.refl32_stride;
+    qa.tile_rows = trs;
+    qa.tile_stride = refl_tile_stride<float>(trs, slot_elems((int)m, false));
+    qa.slot = slot_elems((int)m, false);
     qa.Y = sa.Y;
     qa.y_stride = 2 * m * m;
     qa.X = Xw;
@@ -1111,23 +1145,30 @@ hipError_t solve_mixed(shs_handle *h, int64_t s, const double *shifts, double to
         da.E = at<float>(work, L.e32);
         da.e_stride = 2 * n * m;
         da.refl = at<float>(work, L.refl32);
-        da.refl_stride = g32d.stride;
+        da.refl_stride = L.refl32_stride;
         da.Y = at<float>(work, L.yd32);
         da.y_stride = 2 * n * m;
         da.status = st2;
         da.dcount = cout;
-        {
+        QstarArgs<float> dq{};
+        if (L.blk32_dense) {
+            // blocked, N_blk beside M_blk
+            e = sweep_blocked<float>(h, s, out, cout, shifts, B32, da, st, at<float>(work, L.e32), h->H32,
+                                     PH_SWEEP32D);
+            if (e != hipSuccess) return e;
+            dq.tile_rows = trd;
+            dq.tile_stride = refl_tile_stride<float>(trd, slot_elems((int)m, true));
+        } else {
             PhaseScope ps(h, PH_SWEEP32D, s, st);
             if (!launch_sweep((int)m, true, da, st)) return hipErrorInvalidValue;
+            dq.tile_rows = g32d.g.tile_rows;
+            dq.tile_stride = g32d.g.tile_stride;
         }
-        QstarArgs<float> dq{};
         dq.n = (int)n;
         dq.count = (int)s;
         dq.list = out;
         dq.refl = da.refl;
-        dq.refl_stride = g32d.stride;
-        dq.tile_rows = g32d.g.tile_rows;
-        dq.tile_stride = g32d.g.tile_stride;
+        dq.refl_stride = L.refl32_stride;
         dq.slot = g32d.g.slot;
         dq.Y = da.Y;
         dq.y_stride = 2 * n * m;

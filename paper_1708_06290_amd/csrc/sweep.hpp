@@ -96,9 +96,10 @@ struct SweepArgs {
 };
 
 // Compile-time shape of one kernel instance.
-template <typename T, int M, bool DENSE>
+template <typename T, int M, bool DENSE, int RB = 0>
 struct SweepShape {
-    static constexpr int R = rows_per_lane<T, M, DENSE>();
+    // RB > 0 overrides the rows per lane (the blocked tile kernels)
+    static constexpr int R = RB > 0 ? RB : rows_per_lane<T, M, DENSE>();
     static constexpr int TT = kWave * R;
     static constexpr int S = slot_elems(M, DENSE);
     static constexpr int EM = DENSE ? M : 1;
@@ -314,16 +315,16 @@ __device__ __forceinline__ void pivot_row_slot(const T (&wr)[R][M + 1], const T 
 
 // One tile step k (phase Q = k mod (m+1)); RP >= 0: the pivot is known to
 // be in slot RP, and only slots 0 .. RP are updated.
-template <typename T, int M, bool DENSE, int Q, int RP>
+template <typename T, int M, bool DENSE, int Q, int RP, int RB = 0>
 __device__ __forceinline__ void tri_step(int k, int k_lo, int n, int lo, int lane, const T *H, int64_t ldh, T sgr,
                                          T sgi, T *rf, int64_t tstride, T *Y, T *lds_rs,
-                                         T (&wr)[SweepShape<T, M, DENSE>::R][M + 1],
-                                         T (&wi)[SweepShape<T, M, DENSE>::R][M + 1],
-                                         T (&er)[SweepShape<T, M, DENSE>::R][SweepShape<T, M, DENSE>::EM],
-                                         T (&ei)[SweepShape<T, M, DENSE>::R][SweepShape<T, M, DENSE>::EM],
-                                         T (&nh)[SweepShape<T, M, DENSE>::R], bool &singular, bool &nonfinite)
+                                         T (&wr)[SweepShape<T, M, DENSE, RB>::R][M + 1],
+                                         T (&wi)[SweepShape<T, M, DENSE, RB>::R][M + 1],
+                                         T (&er)[SweepShape<T, M, DENSE, RB>::R][SweepShape<T, M, DENSE, RB>::EM],
+                                         T (&ei)[SweepShape<T, M, DENSE, RB>::R][SweepShape<T, M, DENSE, RB>::EM],
+                                         T (&nh)[SweepShape<T, M, DENSE, RB>::R], bool &singular, bool &nonfinite)
 {
-    using Sh = SweepShape<T, M, DENSE>;
+    using Sh = SweepShape<T, M, DENSE, RB>;
     constexpr int R = Sh::R, TT = Sh::TT, S = Sh::S, EM = Sh::EM, NP = Sh::NP;
     T ch[R];
 #pragma unroll
@@ -403,16 +404,16 @@ __device__ __forceinline__ void tri_step(int k, int k_lo, int n, int lo, int lan
 // higher slots are finished).  It unrolls the step body R times over; the
 // per-shift sweep keeps the plain form, because beside its stream phase the
 // R copies spill in FP32 (R = 8 there).
-template <typename T, int M, bool DENSE, bool SLOTS = false>
+template <typename T, int M, bool DENSE, bool SLOTS = false, int RB = 0>
 __device__ __forceinline__ void tri_phase(int n, int lo, int hi, int lane, const T *H, int64_t ldh, T sgr, T sgi,
                                           T *rf, int64_t tstride, T *Y, T *lds_rs,
-                                          T (&wr)[SweepShape<T, M, DENSE>::R][M + 1],
-                                          T (&wi)[SweepShape<T, M, DENSE>::R][M + 1],
-                                          T (&er)[SweepShape<T, M, DENSE>::R][SweepShape<T, M, DENSE>::EM],
-                                          T (&ei)[SweepShape<T, M, DENSE>::R][SweepShape<T, M, DENSE>::EM],
+                                          T (&wr)[SweepShape<T, M, DENSE, RB>::R][M + 1],
+                                          T (&wi)[SweepShape<T, M, DENSE, RB>::R][M + 1],
+                                          T (&er)[SweepShape<T, M, DENSE, RB>::R][SweepShape<T, M, DENSE, RB>::EM],
+                                          T (&ei)[SweepShape<T, M, DENSE, RB>::R][SweepShape<T, M, DENSE, RB>::EM],
                                           bool &singular, bool &nonfinite)
 {
-    using Sh = SweepShape<T, M, DENSE>;
+    using Sh = SweepShape<T, M, DENSE, RB>;
     constexpr int R = Sh::R, TT = Sh::TT, S = Sh::S, EM = Sh::EM, NP = Sh::NP;
     const int k_end = lo;
     if (hi - 1 >= k_end) {
@@ -426,7 +427,7 @@ __device__ __forceinline__ void tri_phase(int n, int lo, int hi, int lane, const
                     constexpr int st = decltype(sc)::value;
                     const int k = kg - st;
                     if (k <= k_hi && k >= k_lo)
-                        tri_step<T, M, DENSE, M - st, -1>(k, k_lo, n, lo, lane, H, ldh, sgr, sgi, rf, tstride, Y,
+                        tri_step<T, M, DENSE, M - st, -1, RB>(k, k_lo, n, lo, lane, H, ldh, sgr, sgi, rf, tstride, Y,
                                                           lds_rs, wr, wi, er, ei, nh, singular, nonfinite);
                 });
             }
@@ -441,7 +442,7 @@ __device__ __forceinline__ void tri_phase(int n, int lo, int hi, int lane, const
                             constexpr int st = decltype(sc)::value;
                             const int k = kg - st;
                             if (k <= s_hi && k >= s_lo)
-                                tri_step<T, M, DENSE, M - st, RP>(k, k_lo, n, lo, lane, H, ldh, sgr, sgi, rf, tstride,
+                                tri_step<T, M, DENSE, M - st, RP, RB>(k, k_lo, n, lo, lane, H, ldh, sgr, sgi, rf, tstride,
                                                                   Y, lds_rs, wr, wi, er, ei, nh, singular, nonfinite);
                         });
                     }

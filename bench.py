@@ -244,29 +244,35 @@ def main():
         if kernels:
             top = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
             roof = {"kernel": top, **kernels[top]}
-    # the mixed form's kernels: per-shift FP32 sweeps (structured, then dense
-    # right-hand side for the corrections), FP64 residuals
+    # the mixed form's kernels: the blocked FP32 sweeps (FP32 tile kernels and
+    # the all-shift update on the FP32 matrix cores, for the structured sweep
+    # and for the dense-right-hand-side corrections) and the FP64 residuals.
+    # The update's algorithmic flops per shift are the FP64 solve's (same
+    # schedule, same tile height at this m), twice that for a correction
+    # (4m instead of 2m real columns per shift).
     mixed_kernels = {}
     if "mixed" in results:
         r = results["mixed"]
         ph, calls = r["phase_ms_per_step"], r["launches_per_step"]
         # shift-solves of the correction sweeps; each also gets one more residual
         nd = r["shifts_per_step"].get("sweep32_dense_shifts", 0.0)
+        upd_ps = (results["fp64"]["flops_per_step"].get("sweep_update_flops", 0.0) / s) if "fp64" in results else 0.0
         cand = [
-            (f"sweep_kernel<float,{m},false>", "alu", FP32_PEAK_TFLOPS, ph.get("sweep32_ms", 0.0),
-             calls.get("sweep32_calls", 0), sweep_flops(n, m) * s),
-            (f"sweep_kernel<float,{m},true>", "alu", FP32_PEAK_TFLOPS, ph.get("sweep32_dense_ms", 0.0),
-             calls.get("sweep32_dense_calls", 0), (12.0 * m + 6.0) * n * n * nd),
+            ("zupd32_kernel (structured + corrections)", "mfma", FP32_PEAK_TFLOPS, ph.get("sweep_update_ms", 0.0),
+             calls.get("sweep_update_calls", 0), upd_ps * (s + 2.0 * nd)),
             ("residual_mfma_kernel", "mfma", FP64_PEAK_TFLOPS, ph.get("residual_ms", 0.0),
              calls.get("residual_calls", 0), residual_flops(n, m) * (s + nd)),
         ]
         for name, bound, peak, ms, nl, fl in cand:
-            if ms <= 0 or nl <= 0:
+            if ms <= 0 or nl <= 0 or fl <= 0:
                 continue
             achieved = fl / (ms * 1e-3) / 1e12
             mixed_kernels[name] = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                                    "frac": round(achieved / peak, 4), "ms_per_step": round(ms, 3),
                                    "launches_per_step": nl}
+        mixed_kernels["blk_tri_kernel<float> (structured + corrections)"] = {
+            "bound": "alu", "ms_per_step": round(ph.get("sweep_tile_ms", 0.0), 3),
+            "launches_per_step": calls.get("sweep_tile_calls", 0)}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -62,7 +62,7 @@ namespace shs {
 
 __host__ __device__ constexpr int blk_width(int m)
 {
-    return m <= 1 ? 2 : (m <= 2 ? 4 : (m <= 4 ? 8 : (m <= 8 ? 16 : 32)));
+    return m <= 1 ? 2 : (m <= 2 ? 4 : (m <= 4 ? 8 : (m <= 8 ? 16 : (m <= 16 ? 32 : 64))));
 }
 
 // Real columns per shift of the carried-column array: 2m for the carried
@@ -365,6 +365,9 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
             // offset keeps the compiler from hoisting all the LDS reads out
             // of the row loop into registers
             constexpr bool PF = AW <= 16;
+            // output columns per pass: all of them up to 32, else 16 at a
+            // time (the row itself stays in registers)
+            constexpr int QC = AW > 32 ? 16 : AW;
             T o[AW];
             if (PF && lane < nrows) {
 #pragma unroll
@@ -373,39 +376,51 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
 #pragma unroll 1
             for (int p = lane; p < nrows; p += kWave) {
                 T *row = bb + (int64_t)p * a.ldb;
-                T on[AW], nw[AW];
+                T on[PF ? AW : 1];
                 const int pn = p + kWave < nrows ? p + kWave : p;
 #pragma unroll
                 for (int q = 0; q < AW; ++q) {
                     if constexpr (PF) on[q] = bb[(int64_t)pn * a.ldb + q];
                     else o[q] = row[q];
-                    nw[q] = T(0);
                 }
                 int z = 0;
                 asm volatile("" : "+v"(z));
 #pragma unroll
-                for (int q = 0; q < AW; ++q)
+                for (int qc = 0; qc < AW; qc += QC) {
+                    T nw[QC];
 #pragma unroll
-                    for (int qq = 0; qq < AW; ++qq) nw[qq] = fma(o[q], lds_m2[z + q * W + qq], nw[qq]);
+                    for (int j = 0; j < QC; ++j) nw[j] = T(0);
 #pragma unroll
-                for (int q = 0; q < AW; ++q) {
-                    row[q] = nw[q];
-                    if constexpr (PF) o[q] = on[q];
+                    for (int q = 0; q < AW; ++q)
+#pragma unroll
+                        for (int j = 0; j < QC; ++j) nw[j] = fma(o[q], lds_m2[z + q * W + qc + j], nw[j]);
+#pragma unroll
+                    for (int j = 0; j < QC; ++j) row[qc + j] = nw[j];
+                }
+                if constexpr (PF) {
+#pragma unroll
+                    for (int q = 0; q < AW; ++q) o[q] = on[q];
                 }
             }
-            // M2q <- M2p M2
+            // M2q <- M2p M2: lane k forms row k (its row of M2p loaded once)
             const T *pa = a.M2p + (int64_t)item * W * W;
             T *pm = a.M2q + (int64_t)item * W * W;
-            for (int e = lane; e < AW * AW; e += kWave) {
-                const int k = e / AW, qq = e % AW;
-                // row k of M2p first (its loads in flight together)
+            for (int k = lane; k < AW; k += kWave) {
                 T r[AW];
 #pragma unroll
                 for (int q = 0; q < AW; ++q) r[q] = pa[k * W + q];
-                T acc = T(0);
 #pragma unroll
-                for (int q = 0; q < AW; ++q) acc = fma(r[q], lds_m2[q * W + qq], acc);
-                pm[k * W + qq] = acc;
+                for (int qc = 0; qc < AW; qc += QC) {
+                    T acc[QC];
+#pragma unroll
+                    for (int j = 0; j < QC; ++j) acc[j] = T(0);
+#pragma unroll
+                    for (int q = 0; q < AW; ++q)
+#pragma unroll
+                        for (int j = 0; j < QC; ++j) acc[j] = fma(r[q], lds_m2[q * W + qc + j], acc[j]);
+#pragma unroll
+                    for (int j = 0; j < QC; ++j) pm[k * W + qc + j] = acc[j];
+                }
             }
         }
     }
@@ -435,6 +450,19 @@ struct ZupdArgsT {
     const int *dcount;         // if set, the number of work items is read here (count is an upper bound)
 };
 using ZupdArgs = ZupdArgsT<double>;
+
+// What the direct-to-LDS loads assume: 16-byte aligned groups of rows of H
+// and of columns of Bm (two doubles or four floats), at least one group of
+// rows, K a whole number of chunks unless the padding rows of Bm are zero
+// (the bottom tile).
+template <typename T>
+inline bool zupd_args_ok(int m, const ZupdArgsT<T> &a)
+{
+    constexpr int G = 16 / (int)sizeof(T);
+    return !((a.r0 | a.lo) % G || a.lo - a.r0 < G || a.ldh % G || a.ldb % G || a.ncols % 128 != 0 || a.c0 < 0 ||
+             (a.has_zin && a.K % 16 != 0 && a.nr == 0) || a.K <= 0 || a.n < a.lo ||
+             ((uintptr_t)a.H | (uintptr_t)a.Bm) & 15 || (a.nr != 0 && a.nr != m));
+}
 
 typedef double zupd_dbl4 __attribute__((ext_vector_type(4)));
 
@@ -507,7 +535,10 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgsT<double> a)
     // ---- carried part: Z(rows, shift) * M2(shift) ------------------------------
     if (a.has_zin) {
         constexpr int KZ = W > 16 ? W : 16;   // Z columns feeding one 16-column block
-        constexpr int NS = KZ / 4;            // MFMA k-steps per block
+        constexpr int KP = KZ > 32 ? 16 : KZ;  // of them per pass (registers)
+        constexpr int NS = KP / 4;            // MFMA k-steps per block and pass
+#pragma unroll
+        for (int kpass = 0; kpass < KZ / KP; ++kpass)
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             double az[2][4][NS], bz[2][NS];
@@ -518,7 +549,7 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgsT<double> a)
                 const int zc = W <= 16 ? cb : (cb / W) * W;
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    const int k = 4 * s + lane / 16, q = lane % 16;
+                    const int k = kpass * KP + 4 * s + lane / 16, q = lane % 16;
                     if constexpr (W <= 16) {
                         const int sk = (cb + k) / W, sq = (cb + q) / W;
                         bz[h][s] = sk == sq ? a.M2[(int64_t)sk * W * W + ((cb + k) % W) * W + (cb + q) % W] : 0.0;
@@ -664,8 +695,11 @@ __global__ __launch_bounds__(256, 2) void zupd32_kernel(ZupdArgsT<float> a)
 
     // ---- carried part: Z(rows, shift) * M2(shift) ------------------------------
     if (a.has_zin) {
-        constexpr int KZ = W > 16 ? W : 16;
-        constexpr int NS = KZ / 4;
+        constexpr int KZ = W > 16 ? W : 16;   // Z columns feeding one 16-column block
+        constexpr int KP = KZ > 32 ? 16 : KZ;  // of them per pass (registers)
+        constexpr int NS = KP / 4;            // MFMA k-steps per block and pass
+#pragma unroll
+        for (int kpass = 0; kpass < KZ / KP; ++kpass)
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             float az[2][4][NS], bz[2][NS];
@@ -676,7 +710,7 @@ __global__ __launch_bounds__(256, 2) void zupd32_kernel(ZupdArgsT<float> a)
                 const int zc = W <= 16 ? cb : (cb / W) * W;
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    const int k = 4 * s + lane / 16, q = lane % 16;
+                    const int k = kpass * KP + 4 * s + lane / 16, q = lane % 16;
                     if constexpr (W <= 16) {
                         const int sk = (cb + k) / W, sq = (cb + q) / W;
                         bz[h][s] = sk == sq ? a.M2[(int64_t)sk * W * W + ((cb + k) % W) * W + (cb + q) % W] : 0.f;

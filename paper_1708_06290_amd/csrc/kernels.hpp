@@ -47,12 +47,14 @@ template <typename T> struct BlkTriArgsT;
 using BlkTriArgs = BlkTriArgsT<double>;
 template <typename T> struct ZupdArgsT;
 using ZupdArgs = ZupdArgsT<double>;
-constexpr int kBlkDenseMaxM = 8;
+constexpr int kBlkDenseMaxM = 16;
 bool blk_geometry(bool fp32, int m, bool dense, int *tile_rows, int *width);
 bool launch_blk_tri(int m, bool dense, const BlkTriArgsT<double> &a, hipStream_t st);
 bool launch_blk_tri(int m, bool dense, const BlkTriArgsT<float> &a, hipStream_t st);
 bool launch_zupd(int m, const ZupdArgsT<double> &a, hipStream_t st);
 bool launch_zupd(int m, const ZupdArgsT<float> &a, hipStream_t st);
+bool launch_blk_tri_dense(int m, const BlkTriArgsT<double> &a, hipStream_t st);
+bool launch_blk_tri_dense(int m, const BlkTriArgsT<float> &a, hipStream_t st);
 
 }  // namespace shs
 

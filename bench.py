@@ -387,9 +387,10 @@ def serving_leg(args):
         return out, handles, srv, ids
 
     nreq = args.serve_requests
-    # capacity from a closed burst of up to 256 requests (a smaller burst
-    # over-states it: a few large mixed-precision requests dominate the tail)
-    burst = workloads.request_stream(min(nreq, 256), rate_hz=1e9, seed=workloads.ARRIVAL_SEED + 1)
+    # capacity from a closed burst of up to 1024 requests: the sustained rate
+    # with the queue never empty (a short burst over-states it, its wall time
+    # ending before the large requests' tail is paid)
+    burst = workloads.request_stream(min(nreq, 1024), rate_hz=1e9, seed=workloads.ARRIVAL_SEED + 1)
     cal, _, srv, _ = run(burst, None, "burst")
     srv.close()
     cap = cal["requests"] / cal["wall_s"]

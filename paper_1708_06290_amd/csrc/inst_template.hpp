@@ -1,5 +1,7 @@
 // Instantiates the sweep and Q* kernels for precision REAL_T and the m values
 // M_FIRST..M_LAST, with launcher names suffixed SUFFIX.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace shs {
@@ -28,9 +30,20 @@ struct Inst {
     static bool qstar(bool dense_in, const QstarArgs<REAL_T> &a, hipStream_t st)
     {
         if (dense_in) {
-            constexpr int spw = kWave / MM;
-            const int blocks = (a.count + spw - 1) / spw;
-            hipLaunchKernelGGL((qstar_kernel<REAL_T, MM, true>), dim3(blocks), dim3(kWave), 0, st, a);
+            if (a.count <= 0) return true;
+            // the wave kernel: its chunk must hold a whole phase group plus
+            // the next slot, and a tile at least one phase group
+            const int spw = qstar_dense_spw(a.count, MM);
+            constexpr int S = slot_elems(MM, true);
+            const int cs = (MM + 1) * (std::min((kQstarLds / spw - 1) / S - 1, a.tile_rows) / (MM + 1));
+            if (a.slot == S && a.tile_rows >= MM + 1 && cs >= MM + 1) {
+                hipLaunchKernelGGL((qstar_wave_dense_kernel<REAL_T, MM>), dim3((a.count + spw - 1) / spw),
+                                   dim3(kWave), 0, st, a, spw);
+            } else {
+                constexpr int spl = kWave / MM;
+                hipLaunchKernelGGL((qstar_kernel<REAL_T, MM, true>), dim3((a.count + spl - 1) / spl), dim3(kWave), 0,
+                                   st, a);
+            }
         } else if (a.count > 0) {
             // the kernel reads the structured store's slots (and needs a tile
             // of at least one phase group)

@@ -334,3 +334,154 @@ inline int qstar_spw(int64_t count, int m)
 }
 
 }  // namespace shs
+
+namespace shs {
+
+// Dense y (the correction solves and the transposed systems): X (+)= P_{n-1}
+// ... P_0 y, y the n x m result of a dense-right-hand-side sweep.  The same
+// wave organisation as qstar_wave_kernel: spw shifts per wavefront, lane
+// q m + c owns column c of shift q, the reflector slots staged through LDS in
+// chunks of whole phase groups.  The row entering at step k is y_{k+1},
+// which the dense sweep stored in slot k+1, so a chunk of steps cb .. cb+CS-1
+// stages slots cb .. cb+CS (one more than it applies).  With accumulate set,
+// X += scale[sid] * (the product).
+template <typename T, int M>
+__global__ __launch_bounds__(64) void qstar_wave_dense_kernel(QstarArgs<T> a, int spw)
+{
+    constexpr int NP = M + 1;
+    constexpr int S = slot_elems(M, true);
+    constexpr int CE = kQstarLds;
+    constexpr int PL = CE / kWave;
+    static_assert(CE % kWave == 0 && CE >= S * (NP + 1) + 1, "chunk");
+    __shared__ T lds_ch[CE];
+    const int lane = threadIdx.x;
+    const int n = a.n;
+    // steps per chunk (at most a tile, so a chunk spans two tiles at most)
+    // and LDS stride per shift (odd: the shifts' reads fall in different banks)
+    const int CS = NP * (min((CE / spw - 1) / S - 1, a.tile_rows) / NP);
+    const int RS = (CS + 1) * S + 1;
+    const int gl = kWave / spw;                  // lanes loading one shift's chunk
+    const int lq = lane / gl, ll = lane % gl;    // loader: shift, lane within
+    const int q = lane / M, c = lane % M;        // compute: shift, column
+    const int item = blockIdx.x * spw + q;
+    const int count = a.dcount ? *a.dcount : a.count;
+    if (blockIdx.x * spw >= count) return;   // uniform: no shift of this wave is listed
+    const bool active = q < spw && item < count;
+    const int litem = blockIdx.x * spw + lq;
+    const bool lact = litem < count;
+    const int sid = active ? (a.list ? a.list[item] : item) : 0;
+    const int lsid = lact ? (a.list ? a.list[litem] : litem) : 0;
+    const T *rf = a.refl + (int64_t)lsid * a.refl_stride;
+    double *X = a.X + ((int64_t)sid * M + c) * a.ldx * 2;
+    const double sc = (a.accumulate && a.scale) ? a.scale[sid] : 1.0;
+    const int ce_elems = (CS + 1) * S;   // elements of one shift's chunk
+    const int tt = a.tile_rows;
+    T pre[PL];
+    // slots past n-1 are read from slot n-1 and never used
+    auto fetch = [&](int cb) {
+        const int t0 = cb / tt, kb = (t0 + 1) * tt;   // the chunk spans tiles t0, t0 + 1
+#pragma unroll
+        for (int e = 0; e < PL; ++e) {
+            const int idx0 = e * gl + ll;
+            const int idx = idx0 < ce_elems ? idx0 : ce_elems - 1;
+            const int ks = idx / S, el = idx - ks * S;
+            const int k = min(cb + ks, n - 1);
+            const int t = k < kb ? t0 : t0 + 1;
+            pre[e] = rf[(int64_t)t * a.tile_stride + (int64_t)(k - t * tt) * S + el];
+        }
+    };
+    double yr[NP], yi[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) { yr[j] = 0.0; yi[j] = 0.0; }
+    const int k_last = n - 1 + M;   // steps k >= n only flush the window
+    fetch(0);
+    for (int cb = 0; cb <= k_last; cb += CS) {
+        __syncthreads();            // previous chunk fully read
+#pragma unroll
+        for (int e = 0; e < PL; ++e) {
+            const int idx = e * gl + ll;
+            if (idx < ce_elems) lds_ch[lq * RS + idx] = pre[e];
+        }
+        __syncthreads();
+        if (cb + CS < n) fetch(cb + CS);
+        if (active) {
+            const T *base = lds_ch + q * RS;
+            if (cb == 0) {
+                // phase 0: row 0 (y_0, in slot 0) is logical m
+                yr[M] = (double)base[2 + 2 * M + 2 * c];
+                yi[M] = (double)base[3 + 2 * M + 2 * c];
+            }
+            const int ce = min(k_last + 1, cb + CS);
+            for (int kg = cb; kg < ce; kg += NP) {
+                static_for<NP>([&](auto qc) {
+                    constexpr int Q = decltype(qc)::value;   // k mod (m+1)
+                    const int k = kg + Q;
+                    if (k < ce) {
+                        const T *pv = base + (k - cb) * S;
+                        if (k < n) {
+                            const double tau = (double)pv[0];
+                            double vr[M], vi[M];
+#pragma unroll
+                            for (int j = 0; j < M; ++j) {
+                                vr[j] = (double)pv[2 + 2 * j];
+                                vi[j] = (double)pv[3 + 2 * j];
+                            }
+                            constexpr int pm = (M + Q) % NP;
+                            double dr0 = yr[pm], di0 = yi[pm], dr1 = 0.0, di1 = 0.0;
+#pragma unroll
+                            for (int j = 0; j < M; ++j) {
+                                const int p = (j + Q) % NP;
+                                if (j & 1) {
+                                    dr1 = fma(vr[j], yr[p], fma(vi[j], yi[p], dr1));
+                                    di1 = fma(vr[j], yi[p], fma(-vi[j], yr[p], di1));
+                                } else {
+                                    dr0 = fma(vr[j], yr[p], fma(vi[j], yi[p], dr0));
+                                    di0 = fma(vr[j], yi[p], fma(-vi[j], yr[p], di0));
+                                }
+                            }
+                            const double tr = tau * (dr0 + dr1), ti = tau * (di0 + di1);
+#pragma unroll
+                            for (int j = 0; j < M; ++j) {
+                                const int p = (j + Q) % NP;
+                                yr[p] = fma(-tr, vr[j], fma(ti, vi[j], yr[p]));
+                                yi[p] = fma(-tr, vi[j], fma(-ti, vr[j], yi[p]));
+                            }
+                            yr[pm] -= tr;
+                            yi[pm] -= ti;
+                        }
+                        // row k-m (logical 0, slot Q) is final
+                        const int row = k - M;
+                        if (row >= 0 && row < n) {
+                            double *px = X + 2 * (int64_t)row;
+                            if (a.accumulate) {
+                                px[0] += sc * yr[Q];
+                                px[1] += sc * yi[Q];
+                            } else {
+                                px[0] = yr[Q];
+                                px[1] = yi[Q];
+                            }
+                        }
+                        // row k+1 enters in the freed slot: y_{k+1}, from slot k+1
+                        const bool in = k + 1 < n;
+                        const T *pn = base + (in ? k + 1 - cb : 0) * S;
+                        yr[Q] = in ? (double)pn[2 + 2 * M + 2 * c] : 0.0;
+                        yi[Q] = in ? (double)pn[3 + 2 * M + 2 * c] : 0.0;
+                    }
+                });
+            }
+        }
+    }
+}
+
+// Shifts per wave of the dense Q* pass: about one wave per SIMD, as many
+// shifts as the lanes and a chunk of at least two phase groups per shift allow.
+inline int qstar_dense_spw(int64_t count, int m)
+{
+    const int S = slot_elems(m, true);
+    int spw = 1;
+    while (spw * 2 * m <= kWave && (kQstarLds / (spw * 2) - 1) / S - 1 >= 2 * (m + 1) && count > (int64_t)spw * 1024)
+        spw *= 2;
+    return spw;
+}
+
+}  // namespace shs

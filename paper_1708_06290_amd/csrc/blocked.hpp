@@ -67,8 +67,14 @@ __host__ __device__ constexpr int blk_width(int m)
 
 // Real columns per shift of the carried-column array: 2m for the carried
 // columns z, and with a dense right-hand side 2m more for e (its m columns'
-// real parts, then imaginary parts), rounded up to a power of two.
-__host__ __device__ constexpr int blk_cols(int m, bool dense) { return blk_width(dense ? 2 * m : m); }
+// real parts, then imaginary parts), rounded up to a power of two or 48.
+__host__ __device__ constexpr int blk_cols(int m, bool dense)
+{
+    // 48 rather than 64 for 4m in 33 .. 48: every 16-column block still holds
+    // columns of one shift only, and a quarter of the update is not spent on
+    // padding
+    return dense && 4 * m > 32 && 4 * m <= 48 ? 48 : blk_width(dense ? 2 * m : m);
+}
 
 template <typename T>
 struct BlkTriArgsT {

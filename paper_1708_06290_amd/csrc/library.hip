@@ -142,6 +142,17 @@ struct Layout {
 
 inline size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Columns of the carried-column array for count shifts of w real columns:
+// whole 128-column tiles of the update, and a whole number of shifts, so
+// that every shift a tile touches (padding ones included) has its columns
+// and its carried matrix inside the buffers (w = 48 needs multiples of 384).
+inline int64_t blk_ncols(int64_t w, int64_t count)
+{
+    int64_t unit = 128;
+    while (unit % w != 0) unit += 128;
+    return (w * count + unit - 1) / unit * unit;
+}
+
 // Row tiles per update group of the blocked FP64 sweep.
 constexpr int kBlkGroup = 4;
 
@@ -173,7 +184,7 @@ bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
         int tr = 0, w = 0;
         if (!blk_geometry(false, (int)m, false, &tr, &w)) return false;
         L->blocked = true;
-        L->blk_cols = (w * s + 127) / 128 * 128;
+        L->blk_cols = blk_ncols(w, s);
         // rows of the block transforms, up to whole 16-row chunks
         L->blk_rows = (kBlkGroup * tr + m + 15) / 16 * 16;
         L->zb = take(sizeof(double) * n * L->blk_cols);
@@ -189,7 +200,8 @@ bool layout(const shs_handle *h, int64_t s, int mode, int outputs, Layout *L)
         int trs = 0, ws = 0, trd = 0, wd = 0;
         if (!blk_geometry(true, (int)m, false, &trs, &ws)) return false;
         L->blk32_dense = blk_geometry(true, (int)m, true, &trd, &wd);
-        const int64_t wmax = std::max(ws, wd), cols = (wmax * s + 127) / 128 * 128;
+        const int64_t wmax = std::max(ws, wd);
+        const int64_t cols = std::max(blk_ncols(ws, s), L->blk32_dense ? blk_ncols(wd, s) : 0);
         const int64_t st_s = (n + trs - 1) / trs * refl_tile_stride<float>(trs, slot_elems((int)m, false));
         const int64_t st_d = L->blk32_dense
                                  ? (n + trd - 1) / trd * refl_tile_stride<float>(trd, slot_elems((int)m, true))
@@ -364,6 +376,9 @@ __global__ __launch_bounds__(256) void blk_dense_init_kernel(int n, int m, int W
 {
     const int v = blockIdx.y, q = blockIdx.z;   // item, column within the item
     const int cnt = dcount ? *dcount : count;
+    // an item past the list whose 16-column block holds no listed item is
+    // never read by a launch that stores results (an empty list: none is)
+    if (v >= cnt && (cnt == 0 || (v * W) / 16 > ((cnt * W) - 1) / 16)) return;
     T *z = Z + ((int64_t)v * W + q) * ldz;
     const int c = q - 2 * m;
     const bool re = v < cnt && c >= 0 && c < m, im = v < cnt && c >= m && c < 2 * m;
@@ -392,7 +407,8 @@ hipError_t sweep_blocked(shs_handle *h, int64_t count, const int32_t *dlist, con
     if (!blk_geometry(fp32, m, dense, &tr, &w)) return hipErrorInvalidValue;
     if (count <= 0) return hipSuccess;
     const int ntiles = (n + tr - 1) / tr;
-    const int64_t ncols = (w * count + 127) / 128 * 128;
+    const int64_t ncols = blk_ncols(w, count);
+    if (ncols % 128 != 0 || ncols % w != 0) return hipErrorInvalidValue;
     T *Zb = B.Zb, *Bm = B.Bm, *M2 = B.M2, *M2p = B.M2p, *M2q = B.M2q;
     PhaseScope whole(h, ph, count, st);
     if (dense) {
@@ -775,7 +791,7 @@ bool trans_layout(const shs_handle *h, int64_t s, int64_t r, TransLayout *L)
         // the blocked sweep with a dense right-hand side (Section 3.1, Step 2
         // revisited, with N_blk beside M_blk)
         L->blocked = true;
-        const int64_t cols = (w * nv + 127) / 128 * 128;
+        const int64_t cols = blk_ncols(w, nv);
         L->blk_rows = (kBlkGroup * tr + m + 15) / 16 * 16;
         L->zb = take(sizeof(double) * n * cols);
         L->bm = take(sizeof(double) * L->blk_rows * cols);
@@ -1264,6 +1280,49 @@ __global__ __launch_bounds__(256) void tvec_pack_kernel(int n, int m, int p, con
         double *e = E + (((int64_t)j * m + col) * n + i) * 2;
         e[0] = er;
         e[1] = ei;
+    }
+}
+
+// ---- X <- Q X in blocks of reflectors ------------------------------------
+constexpr int64_t kApplyQBlock = 64;
+
+// Xr(:, c) = Re X(:, c), Xr(:, ncols + c) = Im X(:, c) (Xr: n x 2 ncols, ld n)
+__global__ __launch_bounds__(256) void split_complex_kernel(int n, const double *X, int64_t ld, double *Xr, int ncols)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+    if (i >= n) return;
+    const double *x = X + ((int64_t)c * ld + i) * 2;
+    Xr[(int64_t)c * n + i] = x[0];
+    Xr[(int64_t)(ncols + c) * n + i] = x[1];
+}
+
+__global__ __launch_bounds__(256) void join_complex_kernel(int n, const double *Xr, int ncols, double *X, int64_t ld)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+    if (i >= n) return;
+    double *x = X + ((int64_t)c * ld + i) * 2;
+    x[0] = Xr[(int64_t)c * n + i];
+    x[1] = Xr[(int64_t)(ncols + c) * n + i];
+}
+
+// T of the compact WY form H_0 H_1 ... H_{b-1} = I - V T V^T (T upper
+// triangular, b x b, ld ldt = blockDim.x) from G = V^T V and the taus:
+// T(i, i) = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) G(0:i, i).  One workgroup,
+// thread k owns row k.
+__global__ __launch_bounds__(64) void wy_t_kernel(int b, const double *G, int ldg, const double *tau, double *T)
+{
+    const int k = threadIdx.x, ldt = blockDim.x;
+    for (int e = k; e < ldt * ldt; e += blockDim.x) T[e] = 0.0;
+    __syncthreads();
+    for (int i = 0; i < b; ++i) {
+        const double ti = tau[i];
+        double s = 0.0;
+        if (k < i)
+            for (int l = k; l < i; ++l) s = fma(T[(int64_t)l * ldt + k], G[(int64_t)i * ldg + l], s);
+        __syncthreads();
+        if (k < i) T[(int64_t)i * ldt + k] = -ti * s;
+        if (k == i) T[(int64_t)i * ldt + i] = ti;
+        __syncthreads();
     }
 }
 
@@ -1869,14 +1928,58 @@ int shs_apply_q(const shs_handle *h, int64_t ncols, const double *Xred, int64_t 
     // Q = Q_B Q_A S: X <- S X, then the Q_A reflectors last to first, then Q_B's
     hipLaunchKernelGGL(scale_rows_complex_kernel, dim3(cdiv(n * ncols, 256)), dim3(256), 0, st, (int)n,
                        (int)ncols, Xorig, ldo, (const double *)h->sgn);
-    for (int64_t idx = h->nrefl - 1; idx >= 0; --idx) {
-        const int64_t r0 = refl_start(m, idx);
-        const int64_t L = n - r0;
-        hipLaunchKernelGGL(reflect_complex_kernel, dim3((unsigned)ncols), dim3(256), 0, st, (int)L, (int)r0, Xorig,
-                           ldo, (const double *)(h->V + idx * n + r0), (const double *)(h->tauv + idx));
+    if (h->nrefl < kApplyQBlock || ncols > INT32_MAX / 2) {
+        // a few reflectors: one launch each
+        for (int64_t idx = h->nrefl - 1; idx >= 0; --idx) {
+            const int64_t r0 = refl_start(m, idx);
+            const int64_t L = n - r0;
+            hipLaunchKernelGGL(reflect_complex_kernel, dim3((unsigned)ncols), dim3(256), 0, st, (int)L, (int)r0,
+                               Xorig, ldo, (const double *)(h->V + idx * n + r0), (const double *)(h->tauv + idx));
+        }
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? 0 : SHS_ERR_HIP;
     }
-    hipError_t e = hipGetLastError();
-    return e == hipSuccess ? 0 : SHS_ERR_HIP;
+    // blocks of kApplyQBlock reflectors as I - V T V^T (compact WY), applied
+    // last block first with FP64 matrix-core GEMMs on the real and imaginary
+    // parts of X side by side
+    const int64_t nb = kApplyQBlock, nc2 = 2 * ncols;
+    const size_t part_elems = (size_t)1 << 22;
+    const size_t bytes = sizeof(double) * ((size_t)n * nc2 + 3 * nb * nb + 2 * nb * nc2 + part_elems);
+    void *work = nullptr;
+    RETURN_IF_HIP(hipMallocAsync(&work, bytes, st));
+    double *Xr = static_cast<double *>(work);
+    double *G = Xr + (size_t)n * nc2, *T = G + nb * nb, *W = T + nb * nb, *W2 = W + nb * nc2, *part = W2 + nb * nc2;
+    hipError_t e = hipSuccess;
+    hipLaunchKernelGGL(split_complex_kernel, dim3(cdiv(n, 256), (unsigned)ncols), dim3(256), 0, st, (int)n,
+                       (const double *)Xorig, ldo, Xr, (int)ncols);
+    for (int64_t j0 = (h->nrefl - 1) / nb * nb; j0 >= 0 && e == hipSuccess; j0 -= nb) {
+        // reflector idx starts at row refl_start(m, idx) = idx, so columns
+        // j0 .. j0+bb-1 of V are zero above row j0 + (column - j0)
+        const int bb = (int)std::min<int64_t>(nb, h->nrefl - j0);
+        const int L = (int)(n - j0);
+        const double *Vb = h->V + j0 * n + j0;
+        e = gemm_f64(true, false, bb, bb, L, 1.0, Vb, n, Vb, n, G, nb, false, part, part_elems, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(wy_t_kernel, dim3(1), dim3(nb), 0, st, bb, (const double *)G, (int)nb,
+                               (const double *)(h->tauv + j0), T);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess)
+            e = gemm_f64(true, false, bb, (int)nc2, L, 1.0, Vb, n, Xr + j0, n, W, nb, false, part, part_elems, st);
+        if (e == hipSuccess)
+            e = gemm_f64(false, false, bb, (int)nc2, bb, 1.0, T, nb, W, nb, W2, nb, false, nullptr, 0, st);
+        if (e == hipSuccess)
+            e = gemm_f64(false, false, L, (int)nc2, bb, -1.0, Vb, n, W2, nb, Xr + j0, n, true, nullptr, 0, st);
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(join_complex_kernel, dim3(cdiv(n, 256), (unsigned)ncols), dim3(256), 0, st, (int)n,
+                           (const double *)Xr, (int)ncols, Xorig, ldo);
+        e = hipGetLastError();
+    }
+    const hipError_t e2 = hipFreeAsync(work, st);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return (e == hipErrorOutOfMemory) ? SHS_ERR_NOMEM : SHS_ERR_HIP;
+    return 0;
 }
 
 int shs_get_reduced(const shs_handle *h, double *H, int64_t ldh, double *R, int64_t ldr, double *Ct,

@@ -76,6 +76,12 @@ __host__ __device__ constexpr int blk_cols(int m, bool dense)
     return dense && 4 * m > 32 && 4 * m <= 48 ? 48 : blk_width(dense ? 2 * m : m);
 }
 
+// Columns of one tile of the update GEMM: 128, or 96 for 48-column shifts.
+// Either way a tile holds whole shifts.  That is what lets the update run in
+// place: the carried part of a shift reads all of the shift's columns, and
+// no other workgroup writes them.
+__host__ __device__ constexpr int zupd_bn(int w) { return w == 48 ? 96 : 128; }
+
 template <typename T>
 struct BlkTriArgsT {
     int n;
@@ -465,7 +471,8 @@ template <typename T>
 inline bool zupd_args_ok(int m, const ZupdArgsT<T> &a)
 {
     constexpr int G = 16 / (int)sizeof(T);
-    return !((a.r0 | a.lo) % G || a.lo - a.r0 < G || a.ldh % G || a.ldb % G || a.ncols % 128 != 0 || a.c0 < 0 ||
+    return !((a.r0 | a.lo) % G || a.lo - a.r0 < G || a.ldh % G || a.ldb % G || a.ncols % 128 != 0 ||
+             a.ncols % zupd_bn(blk_cols(m, a.nr != 0)) != 0 || a.c0 < 0 ||
              (a.has_zin && a.K % 16 != 0 && a.nr == 0) || a.K <= 0 || a.n < a.lo ||
              ((uintptr_t)a.H | (uintptr_t)a.Bm) & 15 || (a.nr != 0 && a.nr != m));
 }
@@ -477,8 +484,9 @@ typedef double zupd_dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kZupdLds = 2 * 2 * 16 * 128 * (int)sizeof(double);
 
 // Z(0:lo, :) <- H(0:lo, c0 : c0+K) Bm(0:K, :) + (per shift) Z M2, minus
-// sigma M1 on the rows whose diagonal is in the block.  128 x 128 tiles,
-// 4 waves of 64 x 64 (4 x 4 blocks of v_mfma_f64_16x16x4f64; lane l holds
+// sigma M1 on the rows whose diagonal is in the block.  128 x BN tiles
+// (BN = zupd_bn(W): whole shifts per tile), 4 waves of 64 x BN/2 (4 x BN/32
+// blocks of v_mfma_f64_16x16x4f64; lane l holds
 // A(l%16, l/16), B(l/16, l%16); result register r of lane l is
 // D(4r + l/16, l%16)).
 //
@@ -488,8 +496,8 @@ constexpr int kZupdLds = 2 * 2 * 16 * 128 * (int)sizeof(double);
 // block holds several shifts and M2 acts as a block-diagonal operand; the
 // tile kernel keeps every shift's Z finite (a shift with a non-finite sigma
 // gets a zero block transform), so the zeros never meet a NaN.  A
-// workgroup reads only its own tile of Z, all before it writes, so the
-// update is in place.
+// workgroup reads only its own tile of Z (its shifts' columns), all before
+// it writes, so the update is in place.
 //
 // The main product streams K in chunks of 16 through two LDS stages that
 // the memory system fills directly (global_load_lds_dwordx4: each lane
@@ -499,16 +507,18 @@ constexpr int kZupdLds = 2 * 2 * 16 * 128 * (int)sizeof(double);
 // memory; the fragment reads of 16 consecutive rows or columns are free of
 // bank conflicts.  Rows of the tile at or past lo read row lo-2 and columns
 // past n-1 read column n-1: their products are never stored or meet zero
-// rows of Bm.  Each chunk's loads are issued right after the previous
-// chunk's fragments are in registers and waited for only after its 64
-// MFMAs.
+// rows of Bm.  An LDS row of Bm always takes 128 columns; with BN = 96 the
+// lanes past the tile load its last two columns again.  Each chunk's loads
+// are issued right after the previous chunk's fragments are in registers
+// and waited for only after its 16 NT MFMAs.
 template <int W>
 __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgsT<double> a)
 {
-    constexpr int BM = 128, BN = 128, BK = 16;
+    constexpr int BM = 128, BN = zupd_bn(W), BK = 16;
+    constexpr int NT = BN / 32;   // 16-column blocks per wave
     extern __shared__ double zupd_smem[];
     auto As = reinterpret_cast<double (*)[BK][BM]>(zupd_smem);
-    auto Bs = reinterpret_cast<double (*)[BK][BN]>(zupd_smem + 2 * BK * BM);
+    auto Bs = reinterpret_cast<double (*)[BK][128]>(zupd_smem + 2 * BK * BM);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int lo = a.lo, K = a.K;
@@ -532,11 +542,11 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgsT<double> a)
     const int count = a.dcount ? *a.dcount : a.count;
     if (j0 >= count * W) return;   // uniform: every column of the tile belongs to no listed item
 
-    zupd_dbl4 acc[4][4];
+    zupd_dbl4 acc[4][NT];
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = zupd_dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int y = 0; y < NT; ++y) acc[x][y] = zupd_dbl4{0.0, 0.0, 0.0, 0.0};
 
     // ---- carried part: Z(rows, shift) * M2(shift) ------------------------------
     if (a.has_zin) {
@@ -546,12 +556,13 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgsT<double> a)
 #pragma unroll
         for (int kpass = 0; kpass < KZ / KP; ++kpass)
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
+        for (int half = 0; half < (NT + 1) / 2; ++half) {
             double az[2][4][NS], bz[2][NS];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int nt = 2 * half + h;
-                const int cb = j0 + wc * 64 + nt * 16;   // first output column of the block
+                if (nt >= NT) break;
+                const int cb = j0 + wc * (BN / 2) + nt * 16;   // first output column of the block
                 const int zc = W <= 16 ? cb : (cb / W) * W;
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
@@ -570,7 +581,7 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgsT<double> a)
                 }
             }
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < 2 && 2 * half + h < NT; ++h)
 #pragma unroll
                 for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -584,7 +595,7 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgsT<double> a)
     // wave w moves rows k = 4w .. 4w+3 of each chunk of both operands
     const int ia = min(i0 + 2 * lane, lo - 2);
     const double *pa = a.H + ia;
-    const double *pb = a.Bm + j0 + 2 * lane;
+    const double *pb = a.Bm + j0 + min(2 * lane, BN - 2);
     auto issue = [&](int b, int k0) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -602,13 +613,13 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgsT<double> a)
     __syncthreads();
     for (int it = 0; it < nk; ++it) {
         const int b = it & 1;
-        double af[4][4], bf[4][4];
+        double af[4][4], bf[4][NT];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) af[s][mt] = As[b][4 * s + lane / 16][wr * 64 + mt * 16 + lane % 16];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) bf[s][nt] = Bs[b][4 * s + lane / 16][wc * 64 + nt * 16 + lane % 16];
+            for (int nt = 0; nt < NT; ++nt) bf[s][nt] = Bs[b][4 * s + lane / 16][wc * (BN / 2) + nt * 16 + lane % 16];
         }
         // the other stage was last read before the previous barrier
         if (it + 1 < nk) issue(b ^ 1, (it + 1) * BK);
@@ -617,7 +628,7 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgsT<double> a)
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
+                for (int nt = 0; nt < NT; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s][mt], bf[s][nt], acc[mt][nt], 0, 0, 0);
         // keep the wait for the next chunk behind this chunk's products
         __builtin_amdgcn_sched_barrier(0);
@@ -630,11 +641,11 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgsT<double> a)
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
+        for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wr * 64 + mt * 16 + 4 * r + lane / 16;
-                const int j = j0 + wc * 64 + nt * 16 + lane % 16;
+                const int j = j0 + wc * (BN / 2) + nt * 16 + lane % 16;
                 if (i >= lo) continue;
                 double v = acc[mt][nt][r];
                 if (i >= lo - m) {
@@ -671,10 +682,11 @@ constexpr int kZupd32Lds = 2 * 2 * 16 * 128 * (int)sizeof(float);
 template <int W>
 __global__ __launch_bounds__(256, 2) void zupd32_kernel(ZupdArgsT<float> a)
 {
-    constexpr int BM = 128, BN = 128, BK = 16;
+    constexpr int BM = 128, BN = zupd_bn(W), BK = 16;
+    constexpr int NT = BN / 32;   // 16-column blocks per wave
     extern __shared__ float zupd32_smem[];
     auto As = reinterpret_cast<float (*)[BK][BM]>(zupd32_smem);
-    auto Bs = reinterpret_cast<float (*)[BK][BN]>(zupd32_smem + 2 * BK * BM);
+    auto Bs = reinterpret_cast<float (*)[BK][128]>(zupd32_smem + 2 * BK * BM);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int lo = a.lo, K = a.K;
@@ -693,11 +705,11 @@ __global__ __launch_bounds__(256, 2) void zupd32_kernel(ZupdArgsT<float> a)
     const int count = a.dcount ? *a.dcount : a.count;
     if (j0 >= count * W) return;
 
-    zupd_flt4 acc[4][4];
+    zupd_flt4 acc[4][NT];
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = zupd_flt4{0.f, 0.f, 0.f, 0.f};
+        for (int y = 0; y < NT; ++y) acc[x][y] = zupd_flt4{0.f, 0.f, 0.f, 0.f};
 
     // ---- carried part: Z(rows, shift) * M2(shift) ------------------------------
     if (a.has_zin) {
@@ -707,12 +719,13 @@ __global__ __launch_bounds__(256, 2) void zupd32_kernel(ZupdArgsT<float> a)
 #pragma unroll
         for (int kpass = 0; kpass < KZ / KP; ++kpass)
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
+        for (int half = 0; half < (NT + 1) / 2; ++half) {
             float az[2][4][NS], bz[2][NS];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int nt = 2 * half + h;
-                const int cb = j0 + wc * 64 + nt * 16;
+                if (nt >= NT) break;
+                const int cb = j0 + wc * (BN / 2) + nt * 16;
                 const int zc = W <= 16 ? cb : (cb / W) * W;
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
@@ -731,7 +744,7 @@ __global__ __launch_bounds__(256, 2) void zupd32_kernel(ZupdArgsT<float> a)
                 }
             }
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < 2 && 2 * half + h < NT; ++h)
 #pragma unroll
                 for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -747,7 +760,7 @@ __global__ __launch_bounds__(256, 2) void zupd32_kernel(ZupdArgsT<float> a)
     const int hk = lane >> 5, p4 = 4 * (lane & 31);
     const int ia = min(i0 + p4, lo - 4);
     const float *pa = a.H + ia;
-    const float *pb = a.Bm + j0 + p4;
+    const float *pb = a.Bm + j0 + min(p4, BN - 4);
     auto issue = [&](int b, int k0) {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
@@ -767,13 +780,13 @@ __global__ __launch_bounds__(256, 2) void zupd32_kernel(ZupdArgsT<float> a)
     __syncthreads();
     for (int it = 0; it < nk; ++it) {
         const int b = it & 1;
-        float af[4][4], bf[4][4];
+        float af[4][4], bf[4][NT];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) af[s][mt] = As[b][4 * s + lane / 16][wr * 64 + mt * 16 + lane % 16];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) bf[s][nt] = Bs[b][4 * s + lane / 16][wc * 64 + nt * 16 + lane % 16];
+            for (int nt = 0; nt < NT; ++nt) bf[s][nt] = Bs[b][4 * s + lane / 16][wc * (BN / 2) + nt * 16 + lane % 16];
         }
         if (it + 1 < nk) issue(b ^ 1, (it + 1) * BK);
 #pragma unroll
@@ -781,7 +794,7 @@ __global__ __launch_bounds__(256, 2) void zupd32_kernel(ZupdArgsT<float> a)
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
+                for (int nt = 0; nt < NT; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s][mt], bf[s][nt], acc[mt][nt], 0, 0, 0);
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_waitcnt(0x0070);
@@ -793,11 +806,11 @@ __global__ __launch_bounds__(256, 2) void zupd32_kernel(ZupdArgsT<float> a)
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
+        for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wr * 64 + mt * 16 + 4 * (lane / 16) + r;
-                const int j = j0 + wc * 64 + nt * 16 + lane % 16;
+                const int j = j0 + wc * (BN / 2) + nt * 16 + lane % 16;
                 if (i >= lo) continue;
                 float v = acc[mt][nt][r];
                 if (i >= lo - m) {

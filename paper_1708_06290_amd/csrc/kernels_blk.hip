@@ -36,8 +36,9 @@ bool launch_zupd(int m, const ZupdArgsT<double> &a, hipStream_t st)
 {
     if (a.lo <= a.r0) return true;
     if (!zupd_args_ok(m, a)) return false;
-    const dim3 grid((unsigned)((a.ncols / 128) * ((a.lo - a.r0 + 127) / 128)));
-    switch (blk_cols(m, a.nr != 0)) {
+    const int w = blk_cols(m, a.nr != 0);
+    const dim3 grid((unsigned)((a.ncols / zupd_bn(w)) * ((a.lo - a.r0 + 127) / 128)));
+    switch (w) {
     case 2: hipLaunchKernelGGL((zupd_kernel<2>), grid, dim3(256), kZupdLds, st, a); return true;
     case 4: hipLaunchKernelGGL((zupd_kernel<4>), grid, dim3(256), kZupdLds, st, a); return true;
     case 8: hipLaunchKernelGGL((zupd_kernel<8>), grid, dim3(256), kZupdLds, st, a); return true;

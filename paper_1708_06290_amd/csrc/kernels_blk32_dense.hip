@@ -32,8 +32,9 @@ bool launch_zupd(int m, const ZupdArgsT<float> &a, hipStream_t st)
 {
     if (a.lo <= a.r0) return true;
     if (!zupd_args_ok(m, a)) return false;
-    const dim3 grid((unsigned)((a.ncols / 128) * ((a.lo - a.r0 + 127) / 128)));
-    switch (blk_cols(m, a.nr != 0)) {
+    const int w = blk_cols(m, a.nr != 0);
+    const dim3 grid((unsigned)((a.ncols / zupd_bn(w)) * ((a.lo - a.r0 + 127) / 128)));
+    switch (w) {
     case 2: hipLaunchKernelGGL((zupd32_kernel<2>), grid, dim3(256), kZupd32Lds, st, a); return true;
     case 4: hipLaunchKernelGGL((zupd32_kernel<4>), grid, dim3(256), kZupd32Lds, st, a); return true;
     case 8: hipLaunchKernelGGL((zupd32_kernel<8>), grid, dim3(256), kZupd32Lds, st, a); return true;

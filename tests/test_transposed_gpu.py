@@ -117,3 +117,39 @@ def test_transposed_full_size_n10000():
         rhs = chat[:, j] @ Go[:, q * m:(q + 1) * m]
         assert oracle.forward_error(lhs, rhs) <= FWD_TOL, j
     sysm.close()
+
+
+def test_transposed_many_shifts_48_columns():
+    """m = r = 10 (48 real columns per shift in the blocked sweep, so update
+    tiles of 96 columns) with 1024 shifts: the update launches hold many more
+    workgroups than the chip runs at once, which is where a tile reading
+    another tile's columns while that one overwrites them in place would
+    show.  Every shift's backward error from the library, and sampled shifts
+    against the oracle with the backward error recomputed here."""
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    n, m, r, s = 2048, 10, 10, 1024
+    print(f"transposed n={n} m={m} r={r} s={s}", flush=True)
+    A, B, C = workloads.system(n, m, 2, 112)
+    sysm = ss.System(A, B, C)
+    H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
+    rng = np.random.default_rng(112)
+    shifts = workloads.imag_axis_shifts(1e-3, 1e3, s)
+    D = rng.standard_normal((n, s * r)) + 1j * rng.standard_normal((n, s * r))
+    res = sysm.solve_transposed(shifts, torch.from_numpy(D).cuda(), r)
+    torch.cuda.synchronize()
+    assert (res.status.cpu().numpy() == 0).all()
+    eta = res.eta.cpu().numpy()
+    print(f"max eta {eta.max():.2e}", flush=True)
+    assert (eta <= ETA_TOL).all(), (np.flatnonzero(eta > ETA_TOL)[:10], eta.max())
+    idx = workloads.subset_indices(s, 4)
+    cols = np.concatenate([np.arange(j * r, (j + 1) * r) for j in idx])
+    Y = res.X[:, torch.as_tensor(cols, device=res.X.device)].cpu().numpy()
+    Ds = D[:, cols]
+    Yo, sto = oracle.solve_rhs(H, Ds, shifts[idx], r, trans=True)
+    assert (sto == 0).all()
+    for q, j in enumerate(idx):
+        c = slice(q * r, (q + 1) * r)
+        assert oracle.forward_error(Y[:, c], Yo[:, c]) <= FWD_TOL, j
+        assert oracle.backward_error(H, Ds[:, c], Y[:, c], shifts[j], trans=True) <= ETA_TOL, j
+    sysm.close()

@@ -170,3 +170,31 @@ def test_modal_system_n10000_all_shifts():
     print(f"modal G: max relative error {err.max():.3e}", flush=True)
     assert (err <= FWD_TOL).all(), (err.argmax(), err.max())
     sysm.close()
+
+
+@pytest.mark.parametrize("m", [9, 12])
+def test_mixed_many_shifts_48_columns(m):
+    """m = 9 and 12 (the dense correction sweeps take 48 real columns per
+    shift and 96-column update tiles) with 1024 imaginary-axis shifts, so
+    that each update launch holds many more workgroups than the chip runs at
+    once: every shift certified by the FP32 sweep and its refinement alone
+    (no FP64 fallback), and every shift's X against the FP64 solve."""
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    n, s = 2048, 1024
+    print(f"mixed n={n} m={m} s={s}", flush=True)
+    A, B, C = workloads.system(n, m, m, 120 + m)
+    sysm = ss.System(A, B, C)
+    shifts = workloads.imag_axis_shifts(1e-3, 1e3, s)
+    r64 = sysm.solve(shifts, mode=ss.SHS_MODE_FP64)
+    rmx = sysm.solve(shifts, mode=ss.SHS_MODE_FP32_REFINE)
+    torch.cuda.synchronize()
+    _certified(r64)
+    _certified(rmx)
+    d = (rmx.X - r64.X).t().abs().square().reshape(s, m, n).sum(dim=(1, 2)).sqrt()
+    ref = r64.X.t().abs().square().reshape(s, m, n).sum(dim=(1, 2)).sqrt()
+    rel = (d / ref).cpu().numpy()
+    print(f"mixed vs FP64: max relative difference {rel.max():.3e}", flush=True)
+    assert (rel <= FWD_TOL).all(), rel.max()
+    _check_samples(sysm, rmx, shifts, workloads.subset_indices(s, 2), m)
+    sysm.close()

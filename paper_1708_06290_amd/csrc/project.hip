@@ -8,7 +8,7 @@
 //      column of the complex V (the caller pairs conjugate points), likewise Wr;
 //   2. orthonormal columns by classical Gram-Schmidt with one
 //      reorthogonalisation (each pass projects against all earlier columns
-//      at once), one workgroup per basis;
+//      at once), spread over workgroups that own ranges of rows;
 //   3. Ar = Wr^T (H Vr), Er = Wr^T Vr, Br = Wr^T R, Cr = Ct Vr as FP64 GEMMs on
 //      the matrix cores (R is nonzero in its first m rows only, so Br needs m
 //      rows of Wr).
@@ -23,8 +23,6 @@ namespace shs {
 
 namespace {
 
-constexpr int kOrthoThreads = 1024;
-constexpr int kOrthoChunk = 16;   // coefficients reduced together
 constexpr size_t kProjPart = (size_t)1 << 22;   // split-K partials (doubles)
 
 inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -42,79 +40,190 @@ __global__ __launch_bounds__(256) void realify_kernel(int n, int r, const double
         out[i] = Z[((int64_t)col * ld + i) * 2 + part];
 }
 
-__device__ inline double block_sum(double v, double *red)
+// Classical Gram-Schmidt with one reorthogonalisation, spread over the
+// chip: for column k of either basis, two passes of
+// v <- v - Q(:, 0:k) (Q(:, 0:k)^T v), then v <- v / ||v||.  Both bases go
+// through the same launches (blockIdx.y); each workgroup owns a fixed range
+// of rows, and a pass is two launches: partial dot products of its rows
+// against the earlier columns (cgs_dot_kernel), then every workgroup sums
+// the partials in the same fixed order and updates its rows
+// (cgs_update_kernel).  The second update also leaves partial squared
+// norms, from which the next column's first launch (or cgs_scale_kernel
+// after the last column) scales column k.  A column that vanishes in exact
+// arithmetic (norm below 2^-40 of its norm before the passes) becomes zeros
+// and is flagged in *flag.  Four launches per column, no host waits.
+constexpr int kCgsThreads = 256;
+constexpr int kCgsRowsMin = 512;   // rows per workgroup, at least
+constexpr int kCgsChunk = 16;      // dot products reduced together
+constexpr int kCgsCoef = 256;      // coefficients staged in LDS at a time
+
+struct CgsArgs {
+    int n, r, rows, G;       // rows per workgroup, workgroups per basis
+    double *Q0, *Q1;         // n x r, ld n
+    double *part;            // [2][G][r] partial dot products of the current pass
+    double *nrm;             // [2][2][G][2] by column parity, basis, workgroup: partial
+                             // ||v||^2 before the passes, after them
+    int *flag;
+};
+
+// Sum of one value over the workgroup, the same order in every workgroup.
+__device__ inline double cgs_block_sum(double v, double *red)
 {
-    // wave sums, then the first wave sums the 16 wave results
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     __syncthreads();
     if (l == 0) red[w] = v;
     __syncthreads();
-    double t = l < kOrthoThreads / 64 ? red[l] : 0.0;
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-    return t;   // every thread holds the total
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kCgsThreads / 64; ++q) s += red[q];
+    return s;
 }
 
-// Orthonormalise the r columns of Q (n x r, ld n) in place: for each column,
-// two passes of v <- v - Q(:, 0:k) (Q(:, 0:k)^T v), then v <- v / ||v||.  A
-// column that vanishes in exact arithmetic (norm below 2^-40 of its norm
-// before the passes) is returned as zeros and flagged in *rank_def.
-__global__ __launch_bounds__(kOrthoThreads) void cgs2_kernel(int n, int r, double *Q0, double *Q1, int *rank_def)
+// sum over the G workgroups' partials x[g * stride], fixed order
+__device__ inline double cgs_partials(const double *x, int G, int stride, double *red)
 {
-    double *Q = blockIdx.x == 0 ? Q0 : Q1;
-    __shared__ double red[kOrthoThreads / 64];
-    __shared__ double part[kOrthoThreads / 64][kOrthoChunk];
-    __shared__ double coef[kOrthoChunk];
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    for (int k = 0; k < r; ++k) {
-        double *v = Q + (int64_t)k * n;
-        double nrm0 = 0.0;
-        for (int i = t; i < n; i += kOrthoThreads) nrm0 = fma(v[i], v[i], nrm0);
-        nrm0 = sqrt(block_sum(nrm0, red));
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int j0 = 0; j0 < k; j0 += kOrthoChunk) {
-                const int nj = min(kOrthoChunk, k - j0);
-                double acc[kOrthoChunk];
+    double s = 0.0;
+    for (int g = threadIdx.x; g < G; g += kCgsThreads) s += x[(int64_t)g * stride];
+    return cgs_block_sum(s, red);
+}
+
+// The partial norms of column k and basis b.  Column k's first launch
+// writes them while other workgroups of the same launch still read column
+// k-1's, hence two sets by column parity.
+__device__ inline double *cgs_nrm(const CgsArgs &a, int k, int b)
+{
+    return a.nrm + ((int64_t)(k & 1) * 2 + b) * a.G * 2;
+}
+
+// Scale column k of basis b on this workgroup's rows (every workgroup
+// computes the same norms from the same partials).
+__device__ inline void cgs_scale(const CgsArgs &a, int b, int k, double *red)
+{
+    double *Q = b ? a.Q1 : a.Q0;
+    const double *nb = cgs_nrm(a, k, b);
+    const double nrm0 = sqrt(cgs_partials(nb, a.G, 2, red));
+    const double nrm = sqrt(cgs_partials(nb + 1, a.G, 2, red));
+    const bool dead = !(nrm > 0x1p-40 * nrm0);
+    const double sc = dead ? 0.0 : 1.0 / nrm;
+    double *v = Q + (int64_t)k * a.n;
+    const int i0 = blockIdx.x * a.rows, i1 = min(a.n, i0 + a.rows);
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += kCgsThreads) v[i] = dead ? 0.0 : v[i] * sc;
+    if (dead && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(a.flag, 1);
+}
+
+// Partial dot products of column k against columns 0 .. k-1 over this
+// workgroup's rows; in the first pass also its partial ||v||^2, after
+// scaling column k-1 (the rows this thread reads below are the ones it
+// scales).
+__global__ __launch_bounds__(kCgsThreads) void cgs_dot_kernel(CgsArgs a, int k, int first)
+{
+    __shared__ double red[kCgsThreads / 64];
+    __shared__ double sums[kCgsChunk];
+    const int b = blockIdx.y, g = blockIdx.x, t = threadIdx.x;
+    if (first && k > 0) cgs_scale(a, b, k - 1, red);
+    const double *Q = b ? a.Q1 : a.Q0;
+    const double *v = Q + (int64_t)k * a.n;
+    const int i0 = g * a.rows, i1 = min(a.n, i0 + a.rows);
+    double *pp = a.part + ((int64_t)b * a.G + g) * a.r;
+    for (int j0 = 0; j0 < k; j0 += kCgsChunk) {
+        const int nj = min(kCgsChunk, k - j0);
+        double acc[kCgsChunk];
 #pragma unroll
-                for (int q = 0; q < kOrthoChunk; ++q) acc[q] = 0.0;
-                for (int i = t; i < n; i += kOrthoThreads) {
-                    const double vi = v[i];
+        for (int q = 0; q < kCgsChunk; ++q) acc[q] = 0.0;
+        for (int i = i0 + t; i < i1; i += kCgsThreads) {
+            const double vi = v[i];
 #pragma unroll
-                    for (int q = 0; q < kOrthoChunk; ++q)
-                        if (q < nj) acc[q] = fma(Q[(int64_t)(j0 + q) * n + i], vi, acc[q]);
-                }
-#pragma unroll
-                for (int q = 0; q < kOrthoChunk; ++q) {
-                    double a = acc[q];
-                    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-                    if (l == 0) part[w][q] = a;
-                }
-                __syncthreads();
-                if (t < nj) {
-                    double s = 0.0;
-                    for (int q = 0; q < kOrthoThreads / 64; ++q) s += part[q][t];
-                    coef[t] = s;
-                }
-                __syncthreads();
-                // classical Gram-Schmidt within the chunk: the coefficients of
-                // the chunk were all taken from the same v
-                for (int i = t; i < n; i += kOrthoThreads) {
-                    double vi = v[i];
-                    for (int q = 0; q < nj; ++q) vi = fma(-coef[q], Q[(int64_t)(j0 + q) * n + i], vi);
-                    v[i] = vi;
-                }
-                __syncthreads();
-            }
+            for (int q = 0; q < kCgsChunk; ++q)
+                if (q < nj) acc[q] = fma(Q[(int64_t)(j0 + q) * a.n + i], vi, acc[q]);
         }
-        double nrm = 0.0;
-        for (int i = t; i < n; i += kOrthoThreads) nrm = fma(v[i], v[i], nrm);
-        nrm = sqrt(block_sum(nrm, red));
-        const bool dead = !(nrm > 0x1p-40 * nrm0);
-        const double sc = dead ? 0.0 : 1.0 / nrm;
-        for (int i = t; i < n; i += kOrthoThreads) v[i] = dead ? 0.0 : v[i] * sc;
-        if (dead && t == 0) atomicOr(rank_def, 1);
+#pragma unroll
+        for (int q = 0; q < kCgsChunk; ++q) {
+            const double s = cgs_block_sum(acc[q], red);
+            if (t == 0) sums[q] = s;
+        }
+        __syncthreads();
+        if (t < nj) pp[j0 + t] = sums[t];
         __syncthreads();
     }
+    if (first) {
+        double s = 0.0;
+        for (int i = i0 + t; i < i1; i += kCgsThreads) s = fma(v[i], v[i], s);
+        s = cgs_block_sum(s, red);
+        if (t == 0) cgs_nrm(a, k, b)[g * 2] = s;
+    }
+}
+
+// v <- v - Q(:, 0:k) c over this workgroup's rows, c the summed partials;
+// after the second pass also its partial ||v||^2.
+__global__ __launch_bounds__(kCgsThreads) void cgs_update_kernel(CgsArgs a, int k, int last)
+{
+    __shared__ double red[kCgsThreads / 64];
+    __shared__ double c[kCgsCoef];
+    const int b = blockIdx.y, g = blockIdx.x, t = threadIdx.x;
+    double *Q = b ? a.Q1 : a.Q0;
+    double *v = Q + (int64_t)k * a.n;
+    const int i0 = g * a.rows, i1 = min(a.n, i0 + a.rows);
+    const double *pb = a.part + (int64_t)b * a.G * a.r;
+    for (int j0 = 0; j0 < k; j0 += kCgsCoef) {
+        const int nj = min(kCgsCoef, k - j0);
+        __syncthreads();   // the previous chunk's coefficients are no longer read
+        if (t < nj) {
+            double s = 0.0;
+            for (int q = 0; q < a.G; ++q) s += pb[(int64_t)q * a.r + j0 + t];
+            c[t] = s;
+        }
+        __syncthreads();
+        for (int i = i0 + t; i < i1; i += kCgsThreads) {
+            double vi = v[i];
+            for (int q = 0; q < nj; ++q) vi = fma(-c[q], Q[(int64_t)(j0 + q) * a.n + i], vi);
+            v[i] = vi;
+        }
+    }
+    if (last) {
+        double s = 0.0;
+        for (int i = i0 + t; i < i1; i += kCgsThreads) s = fma(v[i], v[i], s);
+        s = cgs_block_sum(s, red);
+        if (t == 0) cgs_nrm(a, k, b)[g * 2 + 1] = s;
+    }
+}
+
+__global__ __launch_bounds__(kCgsThreads) void cgs_scale_kernel(CgsArgs a, int k)
+{
+    __shared__ double red[kCgsThreads / 64];
+    cgs_scale(a, blockIdx.y, k, red);
+}
+
+// Workgroups per basis: rows of at least kCgsRowsMin per workgroup, and the
+// partials within the buffer of `cap` doubles.
+inline int cgs_groups(int64_t n, int64_t r, size_t cap)
+{
+    const int64_t by_rows = (n + kCgsRowsMin - 1) / kCgsRowsMin;
+    const int64_t by_buf = (int64_t)(cap / (size_t)(2 * r + 8));
+    return (int)std::max<int64_t>(1, std::min(by_rows, by_buf));
+}
+
+hipError_t cgs2(int n, int r, double *Q0, double *Q1, double *part, size_t cap, int *flag, hipStream_t st)
+{
+    CgsArgs a{};
+    a.n = n;
+    a.r = r;
+    a.G = cgs_groups(n, r, cap);
+    a.rows = (n + a.G - 1) / a.G;
+    a.Q0 = Q0;
+    a.Q1 = Q1;
+    a.part = part;
+    a.nrm = part + (size_t)2 * a.G * r;
+    a.flag = flag;
+    const dim3 grid((unsigned)a.G, 2);
+    for (int k = 0; k < r; ++k) {
+        hipLaunchKernelGGL(cgs_dot_kernel, grid, dim3(kCgsThreads), 0, st, a, k, 1);
+        hipLaunchKernelGGL(cgs_update_kernel, grid, dim3(kCgsThreads), 0, st, a, k, 0);
+        hipLaunchKernelGGL(cgs_dot_kernel, grid, dim3(kCgsThreads), 0, st, a, k, 0);
+        hipLaunchKernelGGL(cgs_update_kernel, grid, dim3(kCgsThreads), 0, st, a, k, 1);
+    }
+    hipLaunchKernelGGL(cgs_scale_kernel, grid, dim3(kCgsThreads), 0, st, a, r - 1);
+    return hipGetLastError();
 }
 
 struct ProjLayout {
@@ -186,8 +295,8 @@ extern "C" int shs_project(shs_handle *h, int64_t r, const double *V, int64_t ld
     hipLaunchKernelGGL(realify_kernel, dim3(std::max<unsigned>(1, std::min<unsigned>(64, (unsigned)((n + 255) / 256))),
                                             (unsigned)r, 2),
                        dim3(256), 0, st, (int)n, (int)r, V, ldv, W, ldw, sel, Vr, Wr);
-    hipLaunchKernelGGL(cgs2_kernel, dim3(2), dim3(kOrthoThreads), 0, st, (int)n, (int)r, Vr, Wr, flag);
     if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = cgs2((int)n, (int)r, Vr, Wr, part, kProjPart, flag, st);
     // Ar = Wr^T (H Vr), Er = Wr^T Vr, Br = Wr(0:m, :)^T R(0:m, :), Cr = Ct Vr
     if (e == hipSuccess)
         e = dgemm(false, false, (int)n, (int)r, (int)n, 1.0, h->H, h->ldh, Vr, n, HV, n, false, part, kProjPart, st);

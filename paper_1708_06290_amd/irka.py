@@ -103,12 +103,21 @@ def irka(system, points, bdir, cdir, iters: int = 30, stream=None) -> IrkaResult
     Br = torch.empty((m, r), dtype=torch.float64, device=dev)
     Cr = torch.empty((r, max(1, p)), dtype=torch.float64, device=dev)
     flag = torch.empty(1, dtype=torch.int32, device=dev)
+    # the two families of solves are independent: the transposed ones go on
+    # a second stream (default priority), so that the latency-bound tile
+    # kernels of one family overlap the other's update GEMMs
+    main = stream if stream is not None else torch.cuda.current_stream(dev)
+    side = torch.cuda.Stream(device=dev)
     for _ in range(iters):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sv = system.solve_vec(P, torch.from_numpy(Bd).to(dev), outputs=SHS_OUT_X | SHS_OUT_ETA, stream=stream)
-        sw = system.solve_transposed_vec(P, torch.from_numpy(Cd).to(dev) if p > 0 else None,
-                                         outputs=SHS_OUT_X | SHS_OUT_ETA, stream=stream)
+        with torch.cuda.stream(main):
+            bd = torch.from_numpy(Bd).to(dev)
+            cd = torch.from_numpy(Cd).to(dev) if p > 0 else None
+            side.wait_stream(main)
+            sv = system.solve_vec(P, bd, outputs=SHS_OUT_X | SHS_OUT_ETA, stream=main)
+        with torch.cuda.stream(side):
+            sw = system.solve_transposed_vec(P, cd, outputs=SHS_OUT_X | SHS_OUT_ETA, stream=side)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         stv = torch.cat([sv.status, sw.status]).cpu().numpy()
@@ -116,7 +125,7 @@ def irka(system, points, bdir, cdir, iters: int = 30, stream=None) -> IrkaResult
             raise ArithmeticError(f"shifted solve failed (status {stv.max()})")
         max_eta = max(max_eta, float(torch.cat([sv.eta, sw.eta]).max().cpu()))
         shs_project(system.handle, sv.X.t(), sw.X.t(), torch.from_numpy(sel).to(dev), Ar, Er, Br, Cr, flag,
-                    stream=stream)
+                    stream=main)
         out = (Ar.t().cpu().numpy(), Er.t().cpu().numpy(), Br.t().cpu().numpy(), Cr.t()[:p].cpu().numpy())
         if int(flag.cpu()[0]):
             raise ArithmeticError("the interpolation bases lost rank")

@@ -284,7 +284,7 @@ def main():
     extra = None
     if not args.no_extra:
         extra = {"c2": workload_leg(workloads.C2, ["fp64", "mixed"], 20, 3),
-                 "c5": workload_leg(workloads.C5, ["mixed"], 3, 1, pspec=True),
+                 "c5": workload_leg(workloads.C5, ["fp64", "mixed"], 3, 1, pspec=True),
                  "irka": irka_leg(args.irka_iters) if args.irka_iters > 0 else None}
 
     head = results.get("fp64") or results.get("mixed")

@@ -67,20 +67,21 @@ __host__ __device__ constexpr int blk_width(int m)
 
 // Real columns per shift of the carried-column array: 2m for the carried
 // columns z, and with a dense right-hand side 2m more for e (its m columns'
-// real parts, then imaginary parts), rounded up to a power of two or 48.
+// real parts, then imaginary parts), rounded up to a power of two, 24 or 48.
+// 24 and 48 (for 17 .. 24 and 33 .. 48 active columns) keep a quarter of
+// the update from being spent on padding; a 16-column block then holds
+// columns of at most two shifts (24) or of one (48).
 __host__ __device__ constexpr int blk_cols(int m, bool dense)
 {
-    // 48 rather than 64 for 4m in 33 .. 48: every 16-column block still holds
-    // columns of one shift only, and a quarter of the update is not spent on
-    // padding
-    return dense && 4 * m > 32 && 4 * m <= 48 ? 48 : blk_width(dense ? 2 * m : m);
+    const int aw = dense ? 4 * m : 2 * m;
+    return aw > 32 && aw <= 48 ? 48 : (aw > 16 && aw <= 24 ? 24 : blk_width(dense ? 2 * m : m));
 }
 
-// Columns of one tile of the update GEMM: 128, or 96 for 48-column shifts.
-// Either way a tile holds whole shifts.  That is what lets the update run in
-// place: the carried part of a shift reads all of the shift's columns, and
-// no other workgroup writes them.
-__host__ __device__ constexpr int zupd_bn(int w) { return w == 48 ? 96 : 128; }
+// Columns of one tile of the update GEMM: 128, or 96 for 24- and 48-column
+// shifts.  Either way a tile, and each half of it, holds whole shifts.  That
+// is what lets the update run in place: the carried part of a shift reads
+// all of the shift's columns, and no other workgroup writes them.
+__host__ __device__ constexpr int zupd_bn(int w) { return w == 24 || w == 48 ? 96 : 128; }
 
 template <typename T>
 struct BlkTriArgsT {
@@ -495,7 +496,9 @@ constexpr int kZupdLds = 2 * 2 * 16 * 128 * (int)sizeof(double);
 // multiplies them by M2 into the accumulators.  For W < 16 a 16-column
 // block holds several shifts and M2 acts as a block-diagonal operand; the
 // tile kernel keeps every shift's Z finite (a shift with a non-finite sigma
-// gets a zero block transform), so the zeros never meet a NaN.  A
+// gets a zero block transform), so the zeros never meet a NaN.  With W = 24
+// a block may end inside one shift and start the next: its operand then
+// covers both shifts' columns, again block-diagonal.  A
 // workgroup reads only its own tile of Z (its shifts' columns), all before
 // it writes, so the update is in place.
 //
@@ -550,7 +553,10 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgsT<double> a)
 
     // ---- carried part: Z(rows, shift) * M2(shift) ------------------------------
     if (a.has_zin) {
-        constexpr int KZ = W > 16 ? W : 16;   // Z columns feeding one 16-column block
+        // Z columns feeding one 16-column block: the shifts the block touches
+        // (W = 24: up to two, the second one's only where the block crosses
+        // into it)
+        constexpr int KZ = W > 16 ? (W % 16 ? 2 * W : W) : 16;
         constexpr int KP = KZ > 32 ? 16 : KZ;  // of them per pass (registers)
         constexpr int NS = KP / 4;            // MFMA k-steps per block and pass
 #pragma unroll
@@ -564,19 +570,24 @@ __global__ __launch_bounds__(256, 2) void zupd_kernel(ZupdArgsT<double> a)
                 if (nt >= NT) break;
                 const int cb = j0 + wc * (BN / 2) + nt * 16;   // first output column of the block
                 const int zc = W <= 16 ? cb : (cb / W) * W;
+                const int zend = W % 16 ? ((cb + 15) / W + 1) * W : zc + KZ;   // past the block's last shift
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     const int k = kpass * KP + 4 * s + lane / 16, q = lane % 16;
+                    const bool kin = W % 16 == 0 || zc + k < zend;
                     if constexpr (W <= 16) {
                         const int sk = (cb + k) / W, sq = (cb + q) / W;
                         bz[h][s] = sk == sq ? a.M2[(int64_t)sk * W * W + ((cb + k) % W) * W + (cb + q) % W] : 0.0;
+                    } else if constexpr (W % 16 != 0) {
+                        const int zk = zc + k, sk = zk / W, sq = (cb + q) / W;
+                        bz[h][s] = kin && sk == sq ? a.M2[(int64_t)sk * W * W + (zk % W) * W + (cb + q) % W] : 0.0;
                     } else {
                         bz[h][s] = a.M2[(int64_t)(cb / W) * W * W + k * W + cb % W + q];
                     }
 #pragma unroll
                     for (int mt = 0; mt < 4; ++mt) {
                         const int i = i0 + wr * 64 + mt * 16 + lane % 16;
-                        az[h][mt][s] = i < lo ? a.Z[(int64_t)(zc + k) * a.ldz + i] : 0.0;
+                        az[h][mt][s] = i < lo && kin ? a.Z[(int64_t)(zc + k) * a.ldz + i] : 0.0;
                     }
                 }
             }
@@ -713,7 +724,10 @@ __global__ __launch_bounds__(256, 2) void zupd32_kernel(ZupdArgsT<float> a)
 
     // ---- carried part: Z(rows, shift) * M2(shift) ------------------------------
     if (a.has_zin) {
-        constexpr int KZ = W > 16 ? W : 16;   // Z columns feeding one 16-column block
+        // Z columns feeding one 16-column block: the shifts the block touches
+        // (W = 24: up to two, the second one's only where the block crosses
+        // into it)
+        constexpr int KZ = W > 16 ? (W % 16 ? 2 * W : W) : 16;
         constexpr int KP = KZ > 32 ? 16 : KZ;  // of them per pass (registers)
         constexpr int NS = KP / 4;            // MFMA k-steps per block and pass
 #pragma unroll
@@ -727,19 +741,24 @@ __global__ __launch_bounds__(256, 2) void zupd32_kernel(ZupdArgsT<float> a)
                 if (nt >= NT) break;
                 const int cb = j0 + wc * (BN / 2) + nt * 16;
                 const int zc = W <= 16 ? cb : (cb / W) * W;
+                const int zend = W % 16 ? ((cb + 15) / W + 1) * W : zc + KZ;   // past the block's last shift
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     const int k = kpass * KP + 4 * s + lane / 16, q = lane % 16;
+                    const bool kin = W % 16 == 0 || zc + k < zend;
                     if constexpr (W <= 16) {
                         const int sk = (cb + k) / W, sq = (cb + q) / W;
                         bz[h][s] = sk == sq ? a.M2[(int64_t)sk * W * W + ((cb + k) % W) * W + (cb + q) % W] : 0.f;
+                    } else if constexpr (W % 16 != 0) {
+                        const int zk = zc + k, sk = zk / W, sq = (cb + q) / W;
+                        bz[h][s] = kin && sk == sq ? a.M2[(int64_t)sk * W * W + (zk % W) * W + (cb + q) % W] : 0.f;
                     } else {
                         bz[h][s] = a.M2[(int64_t)(cb / W) * W * W + k * W + cb % W + q];
                     }
 #pragma unroll
                     for (int mt = 0; mt < 4; ++mt) {
                         const int i = i0 + wr * 64 + mt * 16 + lane % 16;
-                        az[h][mt][s] = i < lo ? a.Z[(int64_t)(zc + k) * a.ldz + i] : 0.f;
+                        az[h][mt][s] = i < lo && kin ? a.Z[(int64_t)(zc + k) * a.ldz + i] : 0.f;
                     }
                 }
             }

@@ -39,6 +39,7 @@ bool launch_zupd(int m, const ZupdArgsT<float> &a, hipStream_t st)
     case 4: hipLaunchKernelGGL((zupd32_kernel<4>), grid, dim3(256), kZupd32Lds, st, a); return true;
     case 8: hipLaunchKernelGGL((zupd32_kernel<8>), grid, dim3(256), kZupd32Lds, st, a); return true;
     case 16: hipLaunchKernelGGL((zupd32_kernel<16>), grid, dim3(256), kZupd32Lds, st, a); return true;
+    case 24: hipLaunchKernelGGL((zupd32_kernel<24>), grid, dim3(256), kZupd32Lds, st, a); return true;
     case 32: hipLaunchKernelGGL((zupd32_kernel<32>), grid, dim3(256), kZupd32Lds, st, a); return true;
     case 48: hipLaunchKernelGGL((zupd32_kernel<48>), grid, dim3(256), kZupd32Lds, st, a); return true;
     case 64: hipLaunchKernelGGL((zupd32_kernel<64>), grid, dim3(256), kZupd32Lds, st, a); return true;

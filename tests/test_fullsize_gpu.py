@@ -173,12 +173,13 @@ def test_modal_system_n10000_all_shifts():
 
 
 @pytest.mark.parametrize("m", [9, 12])
-def test_mixed_many_shifts_48_columns(m):
-    """m = 9 and 12 (the dense correction sweeps take 48 real columns per
-    shift and 96-column update tiles) with 1024 imaginary-axis shifts, so
-    that each update launch holds many more workgroups than the chip runs at
-    once: every shift certified by the FP32 sweep and its refinement alone
-    (no FP64 fallback), and every shift's X against the FP64 solve."""
+def test_mixed_many_shifts_96_column_tiles(m):
+    """m = 9 and 12 (24 real columns per shift in the structured sweeps, 48
+    in the dense correction sweeps, update tiles of 96 columns) with 1024
+    imaginary-axis shifts, so that each update launch holds many more
+    workgroups than the chip runs at once: every shift certified by the FP64
+    solve, and by the FP32 sweep and its refinement alone (no FP64
+    fallback), and every shift's X against the FP64 solve."""
     _need_gpu()
     import paper_1708_06290_amd as ss
     n, s = 2048, 1024

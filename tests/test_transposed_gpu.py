@@ -119,21 +119,23 @@ def test_transposed_full_size_n10000():
     sysm.close()
 
 
-def test_transposed_many_shifts_48_columns():
-    """m = r = 10 (48 real columns per shift in the blocked sweep, so update
-    tiles of 96 columns) with 1024 shifts: the update launches hold many more
-    workgroups than the chip runs at once, which is where a tile reading
-    another tile's columns while that one overwrites them in place would
-    show.  Every shift's backward error from the library, and sampled shifts
-    against the oracle with the backward error recomputed here."""
+@pytest.mark.parametrize("m", [6, 10])
+def test_transposed_many_shifts_96_column_tiles(m):
+    """m = r = 6 and 10 (24 and 48 real columns per shift in the blocked
+    sweep, update tiles of 96 columns) with 1024 shifts: the update launches
+    hold many more workgroups than the chip runs at once, which is where a
+    tile reading another tile's columns while that one overwrites them in
+    place would show.  Every shift's backward error from the library, and
+    sampled shifts against the oracle with the backward error recomputed
+    here."""
     _need_gpu()
     import paper_1708_06290_amd as ss
-    n, m, r, s = 2048, 10, 10, 1024
+    n, r, s = 2048, m, 1024
     print(f"transposed n={n} m={m} r={r} s={s}", flush=True)
-    A, B, C = workloads.system(n, m, 2, 112)
+    A, B, C = workloads.system(n, m, 2, 112 + m)
     sysm = ss.System(A, B, C)
     H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
-    rng = np.random.default_rng(112)
+    rng = np.random.default_rng(112 + m)
     shifts = workloads.imag_axis_shifts(1e-3, 1e3, s)
     D = rng.standard_normal((n, s * r)) + 1j * rng.standard_normal((n, s * r))
     res = sysm.solve_transposed(shifts, torch.from_numpy(D).cuda(), r)

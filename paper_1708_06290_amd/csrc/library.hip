@@ -873,8 +873,9 @@ hipError_t certify(shs_handle *h, int64_t s_list, const int32_t *dlist, const in
     ps0.end();
     {
         PhaseScope ps(h, PH_RESIDUAL, s_list, st);
-        hipLaunchKernelGGL(residual_mfma_kernel, dim3(cdiv(n, 128), cdiv(s_list * nc, 64)), dim3(256), kResidualLds,
-                           st, ra);
+        ra.ncol_tiles = (int)((cdiv(s_list * nc, 64) + 7) / 8 * 8);
+        hipLaunchKernelGGL(residual_mfma_kernel, dim3((unsigned)(cdiv(n, 128) * ra.ncol_tiles)), dim3(256),
+                           kResidualLds, st, ra);
     }
     PhaseScope ps1(h, PH_OTHER, s_list, st);
     hipLaunchKernelGGL(eta_kernel, dim3((unsigned)s_list), dim3(256), 0, st, (int)n, (int)nc, (int)s_list, dcount, dlist,

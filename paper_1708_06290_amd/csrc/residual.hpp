@@ -38,6 +38,7 @@ struct ResidualArgs {
     const int *dcount;          // if set, the number of listed shifts is read here (count is an upper bound)
     const double *E;            // if set: dense right-hand sides, complex, column sid nc + c at E + col lde * 2
     int64_t lde;
+    int ncol_tiles;             // column tiles of residual_mfma_kernel's grid (a multiple of 8)
     unsigned long long *emax;   // with E: per column, max |E|
 };
 
@@ -114,6 +115,7 @@ constexpr int kResidualLds = 2 * 2 * 16 * 128 * (int)sizeof(double);
 // alike) read the same rows of Xt at the same time.  The chunks that cover
 // the workgroup's own rows also carry X(i, :) for those rows, so sigma X and
 // max |x| are taken from LDS there: the epilogue makes no dependent loads.
+// The grid is 1-D, (n / 128 rounded up) x ncol_tiles workgroups.
 __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
 {
     constexpr int BM = 128, BN = 128, BK = 16;
@@ -125,8 +127,27 @@ __global__ __launch_bounds__(256, 2) void residual_mfma_kernel(ResidualArgs a)
     const int nc = a.nc;   // columns per shift
     const int ncols = (a.dcount ? *a.dcount : a.count) * nc;
     const int n = a.n, m = a.m;
-    const int i0 = blockIdx.x * BM;
-    const int w0 = blockIdx.y * (BN / 2);   // first complex column of the tile
+    // Tile order (1-D grid of ny row tiles x nxp column tiles, nxp the
+    // column tiles rounded up to a multiple of 8).  Workgroup L runs on XCD
+    // L mod 8.  For the row tiles of group g (8 consecutive row tiles), XCD x
+    // takes the column tiles c = (x + g) mod 8, + 8, ...: every XCD gets
+    // every row group (whose K ranges differ) and the same number of column
+    // tiles in it, and the padding column tiles past the last (which exit
+    // at once) rotate over the XCDs from group to group.  On an XCD,
+    // consecutive workgroups walk the group's row tiles down one of its
+    // column tiles, then the same rows of its next one: the workgroups
+    // resident on an XCD share the group's rows of H and each column tile's
+    // rows of Xt in its L2.
+    int i0, w0;
+    {
+        const int ny = (n + BM - 1) / BM, ncx = a.ncol_tiles / 8;
+        const int L = blockIdx.x, xcd = L & 7, li = L >> 3;
+        constexpr int GR = 8;
+        const int grp = li / (GR * ncx), r = li - grp * GR * ncx;
+        const int rows = min(GR, ny - grp * GR);
+        i0 = (grp * GR + r % rows) * BM;
+        w0 = ((r / rows) * 8 + ((xcd + grp) & 7)) * (BN / 2);   // first complex column of the tile
+    }
     if (w0 >= ncols) return;                // uniform: the tile holds no listed column
     const int q = lane % 16;
     const bool re_lane = q < 8;

@@ -218,7 +218,9 @@ def main():
         # algorithmic flops of the launches the library made (per step)
         tile_f = r["flops_per_step"].get("sweep_tile_flops", 0.0)
         upd_f = r["flops_per_step"].get("sweep_update_flops", 0.0)
-        w = 2 if m <= 1 else 4 if m <= 2 else 8 if m <= 4 else 16 if m <= 8 else 32
+        # real columns per shift of the structured sweep (2m rounded up to a
+        # power of two, or to 24 for 2m in 17 .. 24), the kernel's template width
+        w = 2 if m <= 1 else 4 if m <= 2 else 8 if m <= 4 else 16 if m <= 8 else 24 if m <= 12 else 32
         cand = [
             (f"zupd_kernel<{w}>", "mfma", ph.get("sweep_update_ms", 0.0), calls.get("sweep_update_calls", 0), upd_f),
             (f"blk_tri_kernel<{m}>", "alu", ph.get("sweep_tile_ms", 0.0), calls.get("sweep_tile_calls", 0), tile_f),

@@ -46,10 +46,12 @@
 // Z holds, for work item (shift) w, the carried columns of every row as 2m
 // real columns w W .. w W + 2m - 1 (real parts, then imaginary parts) of a
 // column-major n x (W items) array; W, the per-shift column stride, is 2m
-// rounded up to a power of two (>= 2), so a 16-column MFMA block holds one
-// shift (W = 16), half of one (W = 32) or several whole ones (W < 16).  The
-// main product never mixes columns; the carried part of W < 16 does, with
-// zero weights (see zupd_kernel).
+// (4m with a dense right-hand side) rounded up to a power of two (>= 2), or
+// to 24 or 48 (blk_cols), so a 16-column MFMA block holds one shift
+// (W = 16), part of one (W = 32, 48, 64), several whole ones (W < 16), or
+// the end of one shift and the start of the next (W = 24).  The main
+// product never mixes columns; the carried part of W < 16 and W = 24 does,
+// with zero weights (see zupd_kernel).
 // The bottom tile's carried columns are
 // plain columns of H - sigma I, so its GEMM folds them into K (K = n_b + m)
 // and reads no Z.

@@ -125,3 +125,75 @@ def test_iterations_interpolate(n, m, p, pairs, iters):
         assert np.linalg.norm((Gs - Grs) @ b[:, i]) <= tol * sc * np.linalg.norm(b[:, i]), i
         assert np.linalg.norm(c[:, i] @ (Gs - Grs)) <= tol * sc * np.linalg.norm(c[:, i]), i
     sysm.close()
+
+
+def _orthonormal(Z):
+    """Orthonormal basis of Z's columns with a positive diagonal in its
+    triangular factor (what Gram-Schmidt produces), from LAPACK's QR."""
+    Q, Rq = np.linalg.qr(Z)
+    return Q * np.sign(np.diag(Rq))[None, :]
+
+
+@pytest.mark.parametrize("n,m,p,ncol", [(700, 3, 2, 5), (2100, 8, 8, 50), (130, 1, 1, 7)])
+def test_projection_against_householder_qr(n, m, p, ncol):
+    """shs_project alone: real bases from selected Re / Im parts of random
+    complex columns, orthonormalised on the GPU (Gram-Schmidt over the whole
+    chip), then W^T H V, W^T V, W^T R, Ct V, against the same products of
+    the bases LAPACK's Householder QR gives (sign-fixed to a positive
+    triangular diagonal), relative Frobenius error <= 1e-11."""
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    from paper_1708_06290_amd._lib import shs_project
+    rng = np.random.default_rng(300 + n)
+    A, B, C = workloads.system(n, m, p, 301 + n)
+    sysm = ss.System(A, B, C)
+    H, R, Ct = (t.cpu().numpy() for t in sysm.reduced())
+    r = 2 * ncol
+    dev = torch.device("cuda", 0)
+    V = rng.standard_normal((n, r)) + 1j * rng.standard_normal((n, r))
+    W = rng.standard_normal((n, r)) + 1j * rng.standard_normal((n, r))
+    sel = np.arange(r, dtype=np.int32)            # Re and Im of columns 0 .. ncol-1
+    Ar = torch.empty((r, r), dtype=torch.float64, device=dev)
+    Er = torch.empty((r, r), dtype=torch.float64, device=dev)
+    Br = torch.empty((m, r), dtype=torch.float64, device=dev)
+    Cr = torch.empty((r, max(1, p)), dtype=torch.float64, device=dev)
+    flag = torch.empty(1, dtype=torch.int32, device=dev)
+    shs_project(sysm.handle, torch.from_numpy(V.T.copy()).to(dev), torch.from_numpy(W.T.copy()).to(dev),
+                torch.from_numpy(sel).to(dev), Ar, Er, Br, Cr, flag)
+    torch.cuda.synchronize()
+    assert int(flag.cpu()[0]) == 0
+    pick = lambda Z: np.stack([Z[:, k >> 1].imag if k & 1 else Z[:, k >> 1].real for k in sel], axis=1)
+    Vq, Wq = _orthonormal(pick(V)), _orthonormal(pick(W))
+    want = {"Ar": Wq.T @ H @ Vq, "Er": Wq.T @ Vq, "Br": Wq.T @ R, "Cr": Ct @ Vq}
+    got = {"Ar": Ar.t().cpu().numpy(), "Er": Er.t().cpu().numpy(), "Br": Br.t().cpu().numpy(),
+           "Cr": Cr.t()[:p].cpu().numpy()}
+    for k in want:
+        err = np.linalg.norm(got[k] - want[k]) / np.linalg.norm(want[k])
+        print(f"{k}: relative error {err:.2e}", flush=True)
+        assert err <= 1e-11, (k, err)
+    sysm.close()
+
+
+def test_projection_flags_a_dependent_column():
+    """A basis column that is a copy of an earlier one vanishes under
+    Gram-Schmidt: shs_project flags the bases as rank deficient."""
+    _need_gpu()
+    import paper_1708_06290_amd as ss
+    from paper_1708_06290_amd._lib import shs_project
+    n, m, p, ncol = 900, 2, 2, 6
+    rng = np.random.default_rng(310)
+    A, B, C = workloads.system(n, m, p, 311)
+    sysm = ss.System(A, B, C)
+    r = 2 * ncol
+    dev = torch.device("cuda", 0)
+    V = rng.standard_normal((n, r)) + 1j * rng.standard_normal((n, r))
+    W = V.copy()
+    W[:, 4] = W[:, 1]                                 # Re / Im of column 4 repeat those of column 1
+    sel = np.arange(r, dtype=np.int32)
+    outs = [torch.empty(s, dtype=torch.float64, device=dev) for s in ((r, r), (r, r), (m, r), (r, p))]
+    flag = torch.empty(1, dtype=torch.int32, device=dev)
+    shs_project(sysm.handle, torch.from_numpy(V.T.copy()).to(dev), torch.from_numpy(W.T.copy()).to(dev),
+                torch.from_numpy(sel).to(dev), *outs, flag)
+    torch.cuda.synchronize()
+    assert int(flag.cpu()[0]) == 1
+    sysm.close()

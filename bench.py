@@ -14,6 +14,14 @@ are resident in HBM before the timed region.  The JSON line also carries the
 roofline of the dominant kernel (the one with the largest time per step among
 the blocked sweep's update GEMM and tile kernel and the FP64 residual) and
 the oracle timed on this host's cores on a bounded sample of shifts.
+
+Beside the timed workload (not part of `value`): the serving mix (a closed
+burst, then Poisson arrivals at 50% and 80% of the measured capacity, with
+latency from arrival), and `other_workloads` at full size: n = 4096, m = 4,
+1000 shifts and the n = 16384, m = 10 complex-plane grid (its structured
+pseudospectrum included), each in both forms, and the interpolation method
+at n = 15000, m = p = 10, r = 100 (`--no-extra` and `--serve-requests 0`
+skip them).
 """
 from __future__ import annotations
 

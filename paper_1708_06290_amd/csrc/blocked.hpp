@@ -79,6 +79,11 @@ __host__ __device__ constexpr int blk_cols(int m, bool dense)
     return aw > 32 && aw <= 48 ? 48 : (aw > 16 && aw <= 24 ? 24 : blk_width(dense ? 2 * m : m));
 }
 
+// The structured block-transform chain of the tile kernel is split over
+// kMblkGroups lane groups up to this m (see blk_tri_kernel).
+constexpr int kMblkGroups = 4;
+constexpr int kMblkSplitMaxM = 8;
+
 // Columns of one tile of the update GEMM: 128, or 96 for 24- and 48-column
 // shifts.  Either way a tile, and each half of it, holds whole shifts.  That
 // is what lets the update run in place: the carried part of a shift reads
@@ -294,69 +299,232 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
                 lds_m2[(M + cp) * W + M + cre] = xr;
             }
         };
-        T ur[NP], ui[NP];
+        if constexpr (DENSE || M > kMblkSplitMaxM) {
+            T ur[NP], ui[NP];
 #pragma unroll
-        for (int p = 0; p < NP; ++p) { ur[p] = (!isn && p == c) ? T(1) : T(0); ui[p] = T(0); }
-        fetch(lo);
-        for (int cb = lo; cb < hi; cb += CS) {
-            // one wave per workgroup: its LDS operations complete in order,
-            // so the chunk can overwrite the previous one in place
+            for (int p = 0; p < NP; ++p) { ur[p] = (!isn && p == c) ? T(1) : T(0); ui[p] = T(0); }
+            fetch(lo);
+            for (int cb = lo; cb < hi; cb += CS) {
+                // one wave per workgroup: its LDS operations complete in order,
+                // so the chunk can overwrite the previous one in place
 #pragma unroll
-            for (int e = 0; e < PL; ++e) {
-                const int idx = e * kWave + lane;
-                if (idx < CE) lds_ch[idx] = pre[e];
-            }
-            if (cb + CS < hi) fetch(cb + CS);
-            if (lane < NL) {
-            const int ce = min(hi, cb + CS);
-            for (int kb = cb; kb < ce; kb += NP) {
-            static_for<NP>([&](auto sc) {
-                constexpr int st = decltype(sc)::value;
-                const int k = kb + st;
-                if (k < ce) {
-                    const T *pv = lds_ch + (k - cb) * S;
-                    const T tau = pv[0];
-                    T vr[M], vi[M];
-#pragma unroll
-                    for (int j = 0; j < M; ++j) { vr[j] = pv[2 + 2 * j]; vi[j] = pv[3 + 2 * j]; }
-                    if constexpr (DENSE) {
-                        // y_k(c) enters at window position m (row k-lo+m)
-                        if (isn) {
-                            ur[(st + M) % NP] += pv[2 + 2 * M + 2 * c];
-                            ui[(st + M) % NP] += pv[3 + 2 * M + 2 * c];
-                        }
-                    }
-                    // s = v^* u over positions j = 0 .. m (v_m = 1); position j in slot (st + j) mod (m+1)
-                    T sr = ur[(st + M) % NP], si = ui[(st + M) % NP];
-#pragma unroll
-                    for (int j = 0; j < M; ++j) {
-                        const int q = (st + j) % NP;
-                        sr = fma(vr[j], ur[q], fma(vi[j], ui[q], sr));
-                        si = fma(vr[j], ui[q], fma(-vi[j], ur[q], si));
-                    }
-                    const T tr = tau * sr, ti = tau * si;
-#pragma unroll
-                    for (int j = 0; j < M; ++j) {
-                        const int q = (st + j) % NP;
-                        ur[q] = fma(-vr[j], tr, fma(vi[j], ti, ur[q]));
-                        ui[q] = fma(-vr[j], ti, fma(-vi[j], tr, ui[q]));
-                    }
-                    ur[(st + M) % NP] -= tr;
-                    ui[(st + M) % NP] -= ti;
-                    emit(k - lo, ur[st], ui[st]);
-                    ur[st] = T(0);
-                    ui[st] = T(0);
+                for (int e = 0; e < PL; ++e) {
+                    const int idx = e * kWave + lane;
+                    if (idx < CE) lds_ch[idx] = pre[e];
                 }
-            });
-            }
-            }
-        }
-        // rows nb .. nb+m-1 are still in the window (row nb+m is the zero row)
-        if (lane < NL) {
+                if (cb + CS < hi) fetch(cb + CS);
+                if (lane < NL) {
+                const int ce = min(hi, cb + CS);
+                for (int kb = cb; kb < ce; kb += NP) {
+                static_for<NP>([&](auto sc) {
+                    constexpr int st = decltype(sc)::value;
+                    const int k = kb + st;
+                    if (k < ce) {
+                        const T *pv = lds_ch + (k - cb) * S;
+                        const T tau = pv[0];
+                        T vr[M], vi[M];
 #pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                const int p = nb + ((q - nb % NP) + NP) % NP;
-                if (p < nb + M) emit(p, ur[q], ui[q]);
+                        for (int j = 0; j < M; ++j) { vr[j] = pv[2 + 2 * j]; vi[j] = pv[3 + 2 * j]; }
+                        if constexpr (DENSE) {
+                            // y_k(c) enters at window position m (row k-lo+m)
+                            if (isn) {
+                                ur[(st + M) % NP] += pv[2 + 2 * M + 2 * c];
+                                ui[(st + M) % NP] += pv[3 + 2 * M + 2 * c];
+                            }
+                        }
+                        // s = v^* u over positions j = 0 .. m (v_m = 1); position j in slot (st + j) mod (m+1)
+                        T sr = ur[(st + M) % NP], si = ui[(st + M) % NP];
+#pragma unroll
+                        for (int j = 0; j < M; ++j) {
+                            const int q = (st + j) % NP;
+                            sr = fma(vr[j], ur[q], fma(vi[j], ui[q], sr));
+                            si = fma(vr[j], ui[q], fma(-vi[j], ur[q], si));
+                        }
+                        const T tr = tau * sr, ti = tau * si;
+#pragma unroll
+                        for (int j = 0; j < M; ++j) {
+                            const int q = (st + j) % NP;
+                            ur[q] = fma(-vr[j], tr, fma(vi[j], ti, ur[q]));
+                            ui[q] = fma(-vr[j], ti, fma(-vi[j], tr, ui[q]));
+                        }
+                        ur[(st + M) % NP] -= tr;
+                        ui[(st + M) % NP] -= ti;
+                        emit(k - lo, ur[st], ui[st]);
+                        ur[st] = T(0);
+                        ui[st] = T(0);
+                    }
+                });
+                }
+                }
+            }
+            // rows nb .. nb+m-1 are still in the window (row nb+m is the zero row)
+            if (lane < NL) {
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    const int p = nb + ((q - nb % NP) + NP) % NP;
+                    if (p < nb + M) emit(p, ur[q], ui[q]);
+                }
+            }
+        } else {
+            // Structured right-hand side: the chain is split over G lane
+            // groups.  Group g (lanes g m .. g m + m-1, column c) runs steps
+            // g h .. g h + h_g - 1 of the tile (h a whole number of phase
+            // groups) from the identity window, so it forms E_g, the rows
+            // those steps finish, and F_g, its final window, for a window
+            // W_g = I at its start.  The true window at the start of group g
+            // is W_g = F_{g-1} W_{g-1} (W_0 = I): the steps are linear in the
+            // window, so group g's true rows are E_g W_g, and the rows nb ..
+            // nb+m-1 left in the window after the last step are W_G.
+            constexpr int G = kMblkGroups;
+            constexpr int CSg = NP * (CS / (G * NP));            // steps per chunk and group
+            static_assert(CSg >= NP && G * CSg * S <= CE, "chunk");
+            static_assert(2 * G * M * M <= CE, "F in the chunk buffer");
+            __shared__ T lds_w[2 * G * M * M];                   // W_1 .. W_G, complex, row-major
+            const int hq = NP * ((nb + G * NP - 1) / (G * NP)); // steps per group, whole phase groups
+            const int g = lane / M, cg = lane % M;
+            const bool act = lane < G * M;
+            const int gs = g * hq;
+            const int hg = act ? max(0, min(hq, nb - gs)) : 0;
+            T *gcr = a.Bm + (int64_t)boff * a.ldb + item * W + cg;
+            // E_g rows straight into Bm (group 0's are final), zero for a bad shift
+            auto emit_raw = [&](int pr, T xr, T xi) {
+                if (bad) xr = xi = T(0);
+                gcr[(int64_t)pr * a.ldb] = xr;
+                gcr[(int64_t)pr * a.ldb + M] = xi;
+            };
+            // chunk of CSg steps of every group, loaded by the whole wave;
+            // steps past the tile read a clamped slot and are not used
+            auto fetch_g = [&](int j0) {
+#pragma unroll
+                for (int e = 0; e < PL; ++e) {
+                    const int idx0 = e * kWave + lane;
+                    const int idx = idx0 < G * CSg * S ? idx0 : G * CSg * S - 1;
+                    const int grp = idx / (CSg * S), rem = idx - grp * (CSg * S);
+                    const int ks = rem / S, el = rem - ks * S;
+                    const int k = lo + min(grp * hq + j0 + ks, nb - 1);
+                    pre[e] = refl_slot<T>(rf, k, TT, tstride, S)[el];
+                }
+            };
+            T ur[NP], ui[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) { ur[p] = (act && p == cg) ? T(1) : T(0); ui[p] = T(0); }
+            fetch_g(0);
+            for (int j0 = 0; j0 < hq; j0 += CSg) {
+                // one wave: the previous chunk's LDS reads are complete
+#pragma unroll
+                for (int e = 0; e < PL; ++e) {
+                    const int idx = e * kWave + lane;
+                    if (idx < G * CSg * S) lds_ch[idx] = pre[e];
+                }
+                if (j0 + CSg < hq) fetch_g(j0 + CSg);
+                for (int kb = 0; kb < CSg; kb += NP) {
+                    static_for<NP>([&](auto sc) {
+                        constexpr int st = decltype(sc)::value;
+                        const int kk = j0 + kb + st;   // step within the group, kk = st (mod m+1)
+                        if (kk < hg) {
+                            const T *pv = lds_ch + (g * CSg + kb + st) * S;
+                            const T tau = pv[0];
+                            T vr[M], vi[M];
+#pragma unroll
+                            for (int j = 0; j < M; ++j) { vr[j] = pv[2 + 2 * j]; vi[j] = pv[3 + 2 * j]; }
+                            T sr = ur[(st + M) % NP], si = ui[(st + M) % NP];
+#pragma unroll
+                            for (int j = 0; j < M; ++j) {
+                                const int q = (st + j) % NP;
+                                sr = fma(vr[j], ur[q], fma(vi[j], ui[q], sr));
+                                si = fma(vr[j], ui[q], fma(-vi[j], ur[q], si));
+                            }
+                            const T tr = tau * sr, ti = tau * si;
+#pragma unroll
+                            for (int j = 0; j < M; ++j) {
+                                const int q = (st + j) % NP;
+                                ur[q] = fma(-vr[j], tr, fma(vi[j], ti, ur[q]));
+                                ui[q] = fma(-vr[j], ti, fma(-vi[j], tr, ui[q]));
+                            }
+                            ur[(st + M) % NP] -= tr;
+                            ui[(st + M) % NP] -= ti;
+                            emit_raw(gs + kk, ur[st], ui[st]);
+                            ur[st] = T(0);
+                            ui[st] = T(0);
+                        }
+                    });
+                }
+            }
+            // F_g (row i = window row hg + i, in slot (hg + i) mod (m+1)) into
+            // the chunk buffer, complex, row-major per group
+            T *lf = lds_ch;
+            if (act) {
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    const int i = ((q - hg) % NP + NP) % NP;
+                    if (i < M) {
+                        lf[2 * ((g * M + i) * M + cg)] = ur[q];
+                        lf[2 * ((g * M + i) * M + cg) + 1] = ui[q];
+                    }
+                }
+            }
+            // W_1 = F_0, W_{g+1} = F_g W_g (lds_w slot g-1 holds W_g); one
+            // wave, so each product reads the previous one's stores
+            for (int e = lane; e < M * M; e += kWave) {
+                lds_w[2 * e] = lf[2 * e];
+                lds_w[2 * e + 1] = lf[2 * e + 1];
+            }
+            for (int gg = 1; gg < G; ++gg) {
+                for (int e = lane; e < M * M; e += kWave) {
+                    const int i = e / M, cc = e % M;
+                    const T *fr = lf + 2 * (gg * M + i) * M;
+                    const T *wp = lds_w + 2 * (gg - 1) * M * M;
+                    T xr = T(0), xi = T(0);
+#pragma unroll
+                    for (int q = 0; q < M; ++q) {
+                        const T ar = fr[2 * q], ai = fr[2 * q + 1];
+                        const T br = wp[2 * (q * M + cc)], bi = wp[2 * (q * M + cc) + 1];
+                        xr = fma(ar, br, fma(-ai, bi, xr));
+                        xi = fma(ar, bi, fma(ai, br, xi));
+                    }
+                    lds_w[2 * (gg * M * M + e)] = xr;
+                    lds_w[2 * (gg * M * M + e) + 1] = xi;
+                }
+            }
+            // the raw rows of groups 1 .. G-1 (written above by other lanes)
+            // become E_g W_g
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            T *brow = a.Bm + (int64_t)boff * a.ldb + item * W;
+            for (int pr = hq + lane; pr < nb; pr += kWave) {
+                const int gg = pr / hq;
+                const T *wp = lds_w + 2 * (gg - 1) * M * M;
+                T *row = brow + (int64_t)pr * a.ldb;
+                T er[M], ei[M];
+#pragma unroll
+                for (int q = 0; q < M; ++q) { er[q] = row[q]; ei[q] = row[M + q]; }
+#pragma unroll
+                for (int cc = 0; cc < M; ++cc) {
+                    T xr = T(0), xi = T(0);
+#pragma unroll
+                    for (int q = 0; q < M; ++q) {
+                        const T br = wp[2 * (q * M + cc)], bi = wp[2 * (q * M + cc) + 1];
+                        xr = fma(er[q], br, fma(-ei[q], bi, xr));
+                        xi = fma(er[q], bi, fma(ei[q], br, xi));
+                    }
+                    row[cc] = bad ? T(0) : xr;
+                    row[M + cc] = bad ? T(0) : xi;
+                }
+            }
+            // rows nb .. nb+m-1: W_G (into K for the bottom tile, else the
+            // carried matrix in its real form)
+            for (int e = lane; e < M * M; e += kWave) {
+                const int i = e / M, cc = e % M;
+                T xr = lds_w[2 * ((G - 1) * M * M + e)], xi = lds_w[2 * ((G - 1) * M * M + e) + 1];
+                if (bad) xr = xi = T(0);
+                if (nb + i < K) {
+                    brow[(int64_t)(nb + i) * a.ldb + cc] = xr;
+                    brow[(int64_t)(nb + i) * a.ldb + M + cc] = xi;
+                } else {
+                    lds_m2[i * W + cc] = xr;
+                    lds_m2[i * W + M + cc] = xi;
+                    lds_m2[(M + i) * W + cc] = -xi;
+                    lds_m2[(M + i) * W + M + cc] = xr;
+                }
             }
         }
         // one wave: its LDS writes above are complete before these reads

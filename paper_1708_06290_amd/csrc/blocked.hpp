@@ -82,10 +82,20 @@ __host__ __device__ constexpr int blk_cols(int m, bool dense)
     return aw > 32 && aw <= 48 ? 48 : (aw > 16 && aw <= 24 ? 24 : blk_width(dense ? 2 * m : m));
 }
 
-// The structured block-transform chain of the tile kernel is split over
-// kMblkGroups lane groups up to this m (see blk_tri_kernel).
-constexpr int kMblkGroups = 4;
+// The block-transform chain of the tile kernel is split over lane groups up
+// to this m (see blk_tri_kernel): 4 groups where the lanes and the reflector
+// chunk (cs steps of m+1-step phase groups) allow it, else 2, else 1 (no
+// split).
 constexpr int kMblkSplitMaxM = 8;
+template <int M, bool DENSE>
+__host__ __device__ constexpr int mblk_groups(int np, int cs)
+{
+    const int lg = DENSE ? 2 * M : M;
+    if (M > kMblkSplitMaxM) return 1;
+    if (4 * lg <= kWave && cs >= 4 * np) return 4;
+    if (2 * lg <= kWave && cs >= 2 * np) return 2;
+    return 1;
+}
 
 // Columns of one tile of the update GEMM: 128, or 96 for 24- and 48-column
 // shifts.  Either way a tile, and each half of it, holds whole shifts.  That
@@ -303,7 +313,8 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
                 lds_m2[(M + cp) * W + M + cre] = xr;
             }
         };
-        if constexpr (DENSE || M > kMblkSplitMaxM) {
+        constexpr int G = mblk_groups<M, DENSE>(NP, CS);
+        if constexpr (G < 2) {
             T ur[NP], ui[NP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) { ur[p] = (!isn && p == c) ? T(1) : T(0); ui[p] = T(0); }
@@ -370,31 +381,39 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
                 }
             }
         } else {
-            // Structured right-hand side: the chain is split over G lane
-            // groups.  Group g (lanes g m .. g m + m-1, column c) runs steps
-            // g h .. g h + h_g - 1 of the tile (h a whole number of phase
-            // groups) from the identity window, so it forms E_g, the rows
-            // those steps finish, and F_g, its final window, for a window
-            // W_g = I at its start.  The true window at the start of group g
-            // is W_g = F_{g-1} W_{g-1} (W_0 = I): the steps are linear in the
-            // window, so group g's true rows are E_g W_g, and the rows nb ..
-            // nb+m-1 left in the window after the last step are W_G.
-            constexpr int G = kMblkGroups;
+            // The chain split over G lane groups.  Group g (lanes g L .. g L +
+            // L-1, L = m, or 2m with a dense right-hand side: the M_blk
+            // columns, then the N_blk ones) runs steps g h .. g h + h_g - 1 of
+            // the tile (h a whole number of phase groups) from the identity
+            // window (M_blk columns) or the zero one (N_blk columns), so it
+            // forms E_g and EN_g, the rows those steps finish, and F_g and
+            // NF_g, its final windows.  The steps are linear in the window
+            // (affine for N_blk, whose y_k enter), so with the true windows at
+            // the start of group g, W_g = F_{g-1} W_{g-1} (W_0 = I) and Nw_g =
+            // F_{g-1} Nw_{g-1} + NF_{g-1} (Nw_0 = 0), group g's true rows are
+            // E_g W_g and E_g Nw_g + EN_g, and the rows nb .. nb+m-1 left in
+            // the window after the last step are W_G and Nw_G.
+            constexpr int LG = DENSE ? 2 * M : M;
+            constexpr int NW = DENSE ? 2 : 1;                     // windows per group
             constexpr int CSg = NP * (CS / (G * NP));            // steps per chunk and group
-            static_assert(CSg >= NP && G * CSg * S <= CE, "chunk");
-            static_assert(2 * G * M * M <= CE, "F in the chunk buffer");
-            __shared__ T lds_w[2 * G * M * M];                   // W_1 .. W_G, complex, row-major
+            static_assert(CSg >= NP && G * CSg * S <= CE && G * LG <= kWave, "chunk");
+            static_assert(2 * NW * G * M * M <= CE, "F in the chunk buffer");
+            // W_1 .. W_G (and Nw_1 .. Nw_G), complex, row-major
+            __shared__ T lds_w[2 * NW * G * M * M];
             const int hq = NP * ((nb + G * NP - 1) / (G * NP)); // steps per group, whole phase groups
-            const int g = lane / M, cg = lane % M;
-            const bool act = lane < G * M;
+            const int g = lane / LG, jl = lane % LG;
+            const bool gisn = DENSE && jl >= M;                  // an N_blk column
+            const int cg = gisn ? jl - M : jl;
+            const bool act = lane < G * LG;
             const int gs = g * hq;
             const int hg = act ? max(0, min(hq, nb - gs)) : 0;
-            T *gcr = a.Bm + (int64_t)boff * a.ldb + item * W + cg;
-            // E_g rows straight into Bm (group 0's are final), zero for a bad shift
+            T *gcr = a.Bm + (int64_t)boff * a.ldb + item * W + (gisn ? 2 * M : 0) + cg;
+            const T gsgn = gisn ? T(-1) : T(1);                  // the operand holds -N_blk
+            // raw rows straight into Bm (group 0's are final), zero for a bad shift
             auto emit_raw = [&](int pr, T xr, T xi) {
                 if (bad) xr = xi = T(0);
-                gcr[(int64_t)pr * a.ldb] = xr;
-                gcr[(int64_t)pr * a.ldb + M] = xi;
+                gcr[(int64_t)pr * a.ldb] = gsgn * xr;
+                gcr[(int64_t)pr * a.ldb + M] = gsgn * xi;
             };
             // chunk of CSg steps of every group, loaded by the whole wave;
             // steps past the tile read a clamped slot and are not used
@@ -411,7 +430,7 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
             };
             T ur[NP], ui[NP];
 #pragma unroll
-            for (int p = 0; p < NP; ++p) { ur[p] = (act && p == cg) ? T(1) : T(0); ui[p] = T(0); }
+            for (int p = 0; p < NP; ++p) { ur[p] = (act && !gisn && p == cg) ? T(1) : T(0); ui[p] = T(0); }
             fetch_g(0);
             for (int j0 = 0; j0 < hq; j0 += CSg) {
                 // one wave: the previous chunk's LDS reads are complete
@@ -431,6 +450,13 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
                             T vr[M], vi[M];
 #pragma unroll
                             for (int j = 0; j < M; ++j) { vr[j] = pv[2 + 2 * j]; vi[j] = pv[3 + 2 * j]; }
+                            if constexpr (DENSE) {
+                                // y_k(c) enters at window position m (row k-lo+m)
+                                if (gisn) {
+                                    ur[(st + M) % NP] += pv[2 + 2 * M + 2 * cg];
+                                    ui[(st + M) % NP] += pv[3 + 2 * M + 2 * cg];
+                                }
+                            }
                             T sr = ur[(st + M) % NP], si = ui[(st + M) % NP];
 #pragma unroll
                             for (int j = 0; j < M; ++j) {
@@ -454,80 +480,97 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
                     });
                 }
             }
-            // F_g (row i = window row hg + i, in slot (hg + i) mod (m+1)) into
-            // the chunk buffer, complex, row-major per group
+            // F_g and NF_g (row i = window row hg + i, in slot (hg + i) mod
+            // (m+1)) into the chunk buffer, complex, row-major per group
             T *lf = lds_ch;
+            auto fidx = [&](int kind, int gg, int i, int cc) { return 2 * (((kind * G + gg) * M + i) * M + cc); };
             if (act) {
 #pragma unroll
                 for (int q = 0; q < NP; ++q) {
                     const int i = ((q - hg) % NP + NP) % NP;
                     if (i < M) {
-                        lf[2 * ((g * M + i) * M + cg)] = ur[q];
-                        lf[2 * ((g * M + i) * M + cg) + 1] = ui[q];
+                        lf[fidx(gisn ? 1 : 0, g, i, cg)] = ur[q];
+                        lf[fidx(gisn ? 1 : 0, g, i, cg) + 1] = ui[q];
                     }
                 }
             }
-            // W_1 = F_0, W_{g+1} = F_g W_g (lds_w slot g-1 holds W_g); one
-            // wave, so each product reads the previous one's stores
-            for (int e = lane; e < M * M; e += kWave) {
-                lds_w[2 * e] = lf[2 * e];
-                lds_w[2 * e + 1] = lf[2 * e + 1];
+            // W_1 = F_0, W_{g+1} = F_g W_g, and Nw_1 = NF_0, Nw_{g+1} = F_g Nw_g
+            // + NF_g (lds_w slot g-1 holds W_g, Nw_g); one wave, so each
+            // product reads the previous one's stores
+            for (int e = lane; e < NW * M * M; e += kWave) {
+                const int kind = e / (M * M), r = e % (M * M);
+                const int s0 = fidx(kind, 0, 0, 0) + 2 * r;
+                lds_w[s0] = lf[s0];
+                lds_w[s0 + 1] = lf[s0 + 1];
             }
             for (int gg = 1; gg < G; ++gg) {
-                for (int e = lane; e < M * M; e += kWave) {
-                    const int i = e / M, cc = e % M;
-                    const T *fr = lf + 2 * (gg * M + i) * M;
-                    const T *wp = lds_w + 2 * (gg - 1) * M * M;
+                for (int e = lane; e < NW * M * M; e += kWave) {
+                    const int kind = e / (M * M), r = e % (M * M), i = r / M, cc = r % M;
+                    const T *fr = lf + fidx(0, gg, i, 0);
                     T xr = T(0), xi = T(0);
+                    if (kind == 1) {
+                        xr = lf[fidx(1, gg, i, cc)];
+                        xi = lf[fidx(1, gg, i, cc) + 1];
+                    }
 #pragma unroll
                     for (int q = 0; q < M; ++q) {
                         const T ar = fr[2 * q], ai = fr[2 * q + 1];
-                        const T br = wp[2 * (q * M + cc)], bi = wp[2 * (q * M + cc) + 1];
+                        const T br = lds_w[fidx(kind, gg - 1, q, cc)], bi = lds_w[fidx(kind, gg - 1, q, cc) + 1];
                         xr = fma(ar, br, fma(-ai, bi, xr));
                         xi = fma(ar, bi, fma(ai, br, xi));
                     }
-                    lds_w[2 * (gg * M * M + e)] = xr;
-                    lds_w[2 * (gg * M * M + e) + 1] = xi;
+                    lds_w[fidx(kind, gg, i, cc)] = xr;
+                    lds_w[fidx(kind, gg, i, cc) + 1] = xi;
                 }
             }
             // the raw rows of groups 1 .. G-1 (written above by other lanes)
-            // become E_g W_g
+            // become E_g W_g (and -(E_g Nw_g + EN_g): the raw N_blk rows are
+            // stored negated)
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             T *brow = a.Bm + (int64_t)boff * a.ldb + item * W;
             for (int pr = hq + lane; pr < nb; pr += kWave) {
                 const int gg = pr / hq;
-                const T *wp = lds_w + 2 * (gg - 1) * M * M;
                 T *row = brow + (int64_t)pr * a.ldb;
                 T er[M], ei[M];
 #pragma unroll
                 for (int q = 0; q < M; ++q) { er[q] = row[q]; ei[q] = row[M + q]; }
 #pragma unroll
-                for (int cc = 0; cc < M; ++cc) {
-                    T xr = T(0), xi = T(0);
+                for (int kind = 0; kind < NW; ++kind) {
 #pragma unroll
-                    for (int q = 0; q < M; ++q) {
-                        const T br = wp[2 * (q * M + cc)], bi = wp[2 * (q * M + cc) + 1];
-                        xr = fma(er[q], br, fma(-ei[q], bi, xr));
-                        xi = fma(er[q], bi, fma(ei[q], br, xi));
+                    for (int cc = 0; cc < M; ++cc) {
+                        T xr = T(0), xi = T(0);
+#pragma unroll
+                        for (int q = 0; q < M; ++q) {
+                            const T br = lds_w[fidx(kind, gg - 1, q, cc)], bi = lds_w[fidx(kind, gg - 1, q, cc) + 1];
+                            xr = fma(er[q], br, fma(-ei[q], bi, xr));
+                            xi = fma(er[q], bi, fma(ei[q], br, xi));
+                        }
+                        if (kind == 0) {
+                            row[cc] = bad ? T(0) : xr;
+                            row[M + cc] = bad ? T(0) : xi;
+                        } else {
+                            row[2 * M + cc] = bad ? T(0) : row[2 * M + cc] - xr;
+                            row[3 * M + cc] = bad ? T(0) : row[3 * M + cc] - xi;
+                        }
                     }
-                    row[cc] = bad ? T(0) : xr;
-                    row[M + cc] = bad ? T(0) : xi;
                 }
             }
-            // rows nb .. nb+m-1: W_G (into K for the bottom tile, else the
-            // carried matrix in its real form)
-            for (int e = lane; e < M * M; e += kWave) {
-                const int i = e / M, cc = e % M;
-                T xr = lds_w[2 * ((G - 1) * M * M + e)], xi = lds_w[2 * ((G - 1) * M * M + e) + 1];
+            // rows nb .. nb+m-1: W_G and Nw_G (into K for the bottom tile,
+            // else the carried matrix in its real form)
+            for (int e = lane; e < NW * M * M; e += kWave) {
+                const int kind = e / (M * M), r = e % (M * M), i = r / M, cc = r % M;
+                const T s = kind ? T(-1) : T(1);
+                T xr = s * lds_w[fidx(kind, G - 1, i, cc)], xi = s * lds_w[fidx(kind, G - 1, i, cc) + 1];
                 if (bad) xr = xi = T(0);
+                const int cre = kind * 2 * M + cc;
                 if (nb + i < K) {
-                    brow[(int64_t)(nb + i) * a.ldb + cc] = xr;
-                    brow[(int64_t)(nb + i) * a.ldb + M + cc] = xi;
+                    brow[(int64_t)(nb + i) * a.ldb + cre] = xr;
+                    brow[(int64_t)(nb + i) * a.ldb + M + cre] = xi;
                 } else {
-                    lds_m2[i * W + cc] = xr;
-                    lds_m2[i * W + M + cc] = xi;
-                    lds_m2[(M + i) * W + cc] = -xi;
-                    lds_m2[(M + i) * W + M + cc] = xr;
+                    lds_m2[i * W + cre] = xr;
+                    lds_m2[i * W + M + cre] = xi;
+                    lds_m2[(M + i) * W + cre] = -xi;
+                    lds_m2[(M + i) * W + M + cre] = xr;
                 }
             }
         }

@@ -24,10 +24,9 @@
 //                   reflectors with the same code as the per-shift sweep
 //                   (stored for the Q* pass), then forms M_blk by applying
 //                   them to [I_m; 0] (lanes c < m, one column each, a sliding
-//                   (m+1)-row window; for m <= 8 and a structured right-hand
-//                   side four lane groups run a quarter of the steps each and
-//                   their rows are combined afterwards) and writes it
-//                   real-ified for the GEMM.
+//                   (m+1)-row window; for m <= 8 two or four lane groups run
+//                   a share of the steps each and their rows are combined
+//                   afterwards) and writes it real-ified for the GEMM.
 //   zupd_kernel     the GEMM above, in place on Z.
 // The top tile's kernel ends with the m x m back substitution, as before.
 //
@@ -250,7 +249,7 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
     if (lane == 0 && (bottom || singular)) a.status[sid] = singular ? 1 : 0;
 
     // ---- M_blk = P_{hi-1} ... P_lo [I_m; 0]: lane c < m owns column c ----------
-    // (the structured form for m <= 8 splits the steps over lane groups, below)
+    // (for m <= 8 the steps are split over lane groups, below)
     // P_k acts on rows k-lo .. k-lo+m of M_blk.  Applied from P_lo upwards, row
     // p is final once P_{lo+p} is done, so each lane keeps a window of m+1
     // rows (row p in slot p mod (m+1)), emits the finished row and lets the

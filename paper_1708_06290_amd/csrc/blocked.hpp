@@ -24,9 +24,10 @@
 //                   reflectors with the same code as the per-shift sweep
 //                   (stored for the Q* pass), then forms M_blk by applying
 //                   them to [I_m; 0] (lanes c < m, one column each, a sliding
-//                   (m+1)-row window; for m <= 8 two or four lane groups run
-//                   a share of the steps each and their rows are combined
-//                   afterwards) and writes it real-ified for the GEMM.
+//                   (m+1)-row window; where mblk_groups allows, two or four
+//                   lane groups run a share of the steps each and their rows
+//                   are combined afterwards) and writes it real-ified for
+//                   the GEMM.
 //   zupd_kernel     the GEMM above, in place on Z.
 // The top tile's kernel ends with the m x m back substitution, as before.
 //
@@ -82,15 +83,17 @@ __host__ __device__ constexpr int blk_cols(int m, bool dense)
 }
 
 // The block-transform chain of the tile kernel is split over lane groups up
-// to this m (see blk_tri_kernel): 4 groups where the lanes and the reflector
-// chunk (cs steps of m+1-step phase groups) allow it, else 2, else 1 (no
-// split).
-constexpr int kMblkSplitMaxM = 8;
+// to these m (see blk_tri_kernel; with a dense right-hand side beyond m = 8
+// the group windows would push the kernel's LDS past what keeps its
+// occupancy): 4 groups where the lanes and the reflector chunk (cs steps of
+// m+1-step phase groups) allow it, else 2, else 1 (no split).
+constexpr int kMblkSplitMaxM = 16;
+constexpr int kMblkSplitMaxMDense = 8;
 template <int M, bool DENSE>
 __host__ __device__ constexpr int mblk_groups(int np, int cs)
 {
     const int lg = DENSE ? 2 * M : M;
-    if (M > kMblkSplitMaxM) return 1;
+    if (M > (DENSE ? kMblkSplitMaxMDense : kMblkSplitMaxM)) return 1;
     if (4 * lg <= kWave && cs >= 4 * np) return 4;
     if (2 * lg <= kWave && cs >= 2 * np) return 2;
     return 1;
@@ -249,7 +252,7 @@ __global__ __launch_bounds__(64, 2) void blk_tri_kernel(BlkTriArgsT<T> a)
     if (lane == 0 && (bottom || singular)) a.status[sid] = singular ? 1 : 0;
 
     // ---- M_blk = P_{hi-1} ... P_lo [I_m; 0]: lane c < m owns column c ----------
-    // (for m <= 8 the steps are split over lane groups, below)
+    // (where mblk_groups allows, the steps are split over lane groups, below)
     // P_k acts on rows k-lo .. k-lo+m of M_blk.  Applied from P_lo upwards, row
     // p is final once P_{lo+p} is done, so each lane keeps a window of m+1
     // rows (row p in slot p mod (m+1)), emits the finished row and lets the
